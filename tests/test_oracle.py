@@ -1,0 +1,304 @@
+"""Pins for the oracle: closed forms, the paper's worked examples, brute force,
+invariants and error paths.  CPU only.
+
+Each test fixes the oracle to something other than itself: a closed form
+derived by hand, a worked example from the paper's text, a second decoder in
+pure Python, direct execution of token lists, or levels recomputed in Python
+from the definition in Sec. 7.1.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import streamgen
+import synth
+
+
+def toks(s):
+    return [tuple(int(v) for v in t) for t in oracle.tokens(s)]
+
+
+def py_levels_and_literals(tokens, n):
+    """Levels from the definition (Sec. 7.1) and a literal-byte map, in Python."""
+    wl = [-1] * n
+    lit = [True] * n
+    out = []
+    for dst, src, ln, _ in tokens:
+        lv = 1 + max(wl[src:src + ln], default=-1)
+        out.append(lv)
+        for k in range(ln):
+            wl[dst + k] = lv
+            lit[dst + k] = False
+    return out, lit
+
+
+def unique_bytes(L, seed=7):
+    rng = np.random.default_rng(seed)
+    return rng.permutation(256)[:L].astype(np.uint8).tobytes()
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("tiebreak", [0, 1])
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_doubling_string_levels_closed_form(tiebreak, k):
+    """u repeated 2^k times (|u| = 16, distinct bytes): the greedy parse is one
+    literal run u then k matches, the j-th at 16*2^j of length 16*2^j from
+    position 0, and its level is exactly j (each doubling reads bytes written
+    by the previous one)."""
+    L = 16
+    x = unique_bytes(L) * (1 << k)
+    s = oracle.encode(x, tiebreak=tiebreak, hash_bits=12)
+    want = [(L << j, 0, L << j, j) for j in range(k)]
+    assert toks(s) == want
+    assert oracle.decode(s).tobytes() == x
+    assert oracle.header_fields(s)["max_level"] == k - 1
+
+
+def test_depth_one_is_two_phase():
+    """With depth limit 1 every match must source literal bytes only, so the
+    doubling string becomes copies of u from position 0, all at level 0."""
+    L, k = 16, 5
+    x = unique_bytes(L) * (1 << k)
+    s = oracle.encode(x, max_depth=1, hash_bits=12)
+    assert toks(s) == [(j * L, 0, L, 0) for j in range(1, 1 << k)]
+    assert oracle.decode(s).tobytes() == x
+
+
+def test_flattening_collapses_doubling_chain():
+    """Within one block, flattening traces every match byte to its literal
+    root, so every piece sources the literal run u at positions 0..15: copies
+    of u, all at level 0 (Sec. 3.3: every in-block source is a literal)."""
+    L, k = 16, 4
+    x = unique_bytes(L) * (1 << k)
+    s = oracle.encode(x, flatten=1, hash_bits=12)
+    t = toks(s)
+    assert all(lv == 0 for *_, lv in t)
+    assert all(src == 0 and ln == L for _, src, ln, _ in t)
+    assert [d for d, *_ in t] == [j * L for j in range(1, 1 << k)]
+    assert oracle.decode(s).tobytes() == x
+
+
+# ------------------------------------------------------ the paper's worked examples
+
+def _w1_input():
+    rng = np.random.default_rng(1234)
+    x = bytearray(rng.integers(0, 256, 6000, dtype=np.uint8).tobytes())
+    x[5100:5132] = x[5000:5032]
+    x[5300:5332] = x[5000:5032]
+    return bytes(x)
+
+
+def test_w1_absolute_offset_example():
+    """Sec. 3.1: bytes at 5,000 referenced from 5,100 (distance 100) and from
+    5,300 (distance 300) are stored both times as the absolute offset 5,000."""
+    x = _w1_input()
+    s = oracle.encode(x, hash_bits=16)
+    t = [tt for tt in toks(s) if tt[0] in (5100, 5300)]
+    assert [(d, src) for d, src, _, _ in t] == [(5100, 5000), (5300, 5000)]
+    assert all(ln == 32 for _, _, ln, _ in t)
+    assert [lv for *_, lv in t] == [0, 0]
+    assert oracle.decode(s).tobytes() == x
+
+
+def test_w2_chain_example():
+    """Sec. 3.3: A copies from B, which copies from literal C.  Without
+    flattening (most-recent tie-break) A sources B at level 1; after
+    flattening A sources C directly at level 0."""
+    x = _w1_input()  # C = 5000.., B = 5100.., A = 5300..
+    s = oracle.encode(x, hash_bits=16, tiebreak=1)
+    t = {d: (src, lv) for d, src, _, lv in toks(s)}
+    assert t[5100] == (5000, 0) and t[5300] == (5100, 1)
+    s = oracle.encode(x, hash_bits=16, tiebreak=1, flatten=1)
+    t = {d: (src, lv) for d, src, _, lv in toks(s)}
+    assert t[5100] == (5000, 0) and t[5300] == (5000, 0)
+
+
+def test_w2_chain_crossing_blocks_keeps_dependency():
+    """Sec. 3.3 limitation: a chain that leaves the block is cut at the first
+    position outside it, so the dependency on the earlier block remains."""
+    x = _w1_input()
+    # blocks of 256 bytes: B (5100) and A (5300) sit in different blocks
+    s = oracle.encode(x, hash_bits=16, tiebreak=1, flatten=1, block_log2=8)
+    t = {d: (src, lv) for d, src, _, lv in toks(s)}
+    # A's source B lies in block 19 (4864..5119) while A lies in block 20:
+    # the trace stops at B, which is itself a level-0 match
+    assert t[5300] == (5100, 1)
+
+
+# ------------------------------------------------------------------ brute force
+
+OPTION_GRID = [
+    dict(),
+    dict(tiebreak=1),
+    dict(flatten=1),
+    dict(flatten=2, tiebreak=1),
+    dict(max_depth=1),
+    dict(max_depth=2, tiebreak=1),
+    dict(max_depth=3, flatten=1),
+    dict(block_log2=3, chunk_log2=0),
+    dict(block_log2=4, flatten=1, tiebreak=1, chunk_log2=1),
+    dict(block_log2=3, max_depth=2, chunk_log2=1),
+]
+
+
+def _all_strings(alpha, maxlen):
+    for L in range(maxlen + 1):
+        for t in itertools.product(alpha, repeat=L):
+            yield bytes(t)
+
+
+def _check_stream(x, s, opts):
+    rep = oracle.check(x, s)
+    assert rep.level_mismatch == 0
+    t = toks(s)
+    py_lv, lit = py_levels_and_literals(t, len(x))
+    assert [lv for *_, lv in t] == py_lv
+    B = 1 << opts.get("block_log2", 20)
+    for dst, src, ln, _ in t:
+        assert src + ln <= dst and ln >= 4
+        assert x[src:src + ln] == x[dst:dst + ln]
+        if opts.get("flatten") == 1:
+            bs = dst // B * B
+            assert all(lit[y] for y in range(max(src, bs), src + ln))
+    if opts.get("max_depth"):
+        assert all(lv <= opts["max_depth"] - 1 for *_, lv in t)
+    return t
+
+
+@pytest.mark.parametrize("opts", OPTION_GRID, ids=lambda o: ",".join(f"{k}={v}" for k, v in o.items()) or "default")
+def test_bruteforce_roundtrip(opts):
+    """Every string over {a,b} up to length 11 and over {a,b,c} up to 7 round-trips
+    under each option set, agrees with the pure-Python decoder and passes the
+    invariants (source before destination, source bytes equal, levels exact,
+    flattening and depth bounds)."""
+    o = dict(hash_bits=8)
+    o.update(opts)
+    n_matched = 0
+    for x in itertools.chain(_all_strings(b"ab", 11), _all_strings(b"abc", 7)):
+        s = oracle.encode(x, **o)
+        assert oracle.decode(s).tobytes() == x
+        assert oracle.refdec(s) == x
+        n_matched += bool(_check_stream(x, s, o))
+    assert n_matched > 100
+
+
+# ------------------------------------------------------ token-level semantics
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_token_streams(seed):
+    """Hand-built streams of random tokens (not from the encoder): the oracle's
+    decode equals direct execution of the tokens and the Python decoder, and
+    its checker recomputes the same levels."""
+    rng = np.random.default_rng(seed)
+    bl = [3, 5, 8, 12][seed % 4]
+    n = int(rng.integers(0, 3000))
+    blocks, lits = streamgen.random_tokens(rng, n, bl, max_len=[6, 40, 300][seed % 3])
+    s, want = streamgen.build(blocks, lits, n, block_log2=bl, chunk_log2=int(rng.integers(0, 5)))
+    assert oracle.decode(s).tobytes() == want
+    assert oracle.refdec(s) == want
+    assert oracle.check(np.frombuffer(want, np.uint8), s).level_mismatch == 0
+    for T in (1, 3):
+        assert oracle.decode_mt(s, T).tobytes() == want
+
+
+def test_edge_cases():
+    for x in [b"", b"a", b"abc", b"abcd", b"aaaaaaaa", bytes(range(256)) * 3]:
+        for o in [dict(), dict(block_log2=3, chunk_log2=0), dict(flatten=1, block_log2=4)]:
+            s = oracle.encode(x, hash_bits=10, **o)
+            assert oracle.decode(s).tobytes() == x
+            assert oracle.refdec(s) == x
+    s = oracle.encode(b"")
+    h = oracle.header_fields(s)
+    assert h["n_blocks"] == 0 and h["comp_bytes"] == 80 and h["n_seq"] == 0
+
+
+def test_sequences_multiple_of_chunk():
+    """n_seq an exact multiple of the chunk size: the trailing run belongs to the last chunk."""
+    blocks = [([(4, 4, 0)] * 4, 3)]
+    lits = bytes(range(19))
+    n = 4 * 8 + 3
+    s, want = streamgen.build(blocks, lits, n, block_log2=8, chunk_log2=1)
+    assert oracle.decode(s).tobytes() == want
+    assert oracle.refdec(s) == want
+
+
+# ----------------------------------------------------------------- error paths
+
+def _valid_small():
+    rng = np.random.default_rng(5)
+    blocks, lits = streamgen.random_tokens(rng, 600, 7)
+    return streamgen.build(blocks, lits, 600, block_log2=7, chunk_log2=2)
+
+
+def test_rejects_overlapping_source():
+    blocks = [([(4, 4, 2)], 0)]  # src 2 + 4 > dst 4
+    with pytest.raises(AssertionError):
+        streamgen.build(blocks, b"abcd", 8, block_log2=8)
+    s, _ = streamgen.build([([(4, 4, 0)], 0)], b"abcd", 8, block_log2=8)
+    bad = s.copy()
+    # the off[] section starts right after the block header + one chunk entry
+    base = int.from_bytes(bad[64:72].tobytes(), "little")
+    off_at = base + 32 + 32
+    bad[off_at:off_at + 4] = np.frombuffer((2).to_bytes(4, "little"), np.uint8)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.decode(bad)
+    assert e.value.code == -3
+
+
+def test_rejects_truncation_and_bad_header():
+    s, _ = _valid_small()
+    for cut in (0, 10, 63, 64, s.size // 2, s.size - 1):
+        with pytest.raises(oracle.OracleError):
+            oracle.decode(s[:cut])
+    bad = s.copy()
+    bad[0] ^= 1
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(bad)
+
+
+def test_random_bit_flips_never_crash():
+    s, want = _valid_small()
+    rng = np.random.default_rng(9)
+    rejected = 0
+    for _ in range(400):
+        bad = s.copy()
+        i = int(rng.integers(0, s.size))
+        bad[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        try:
+            got = oracle.decode(bad)
+        except oracle.OracleError:
+            rejected += 1
+            continue
+        assert got.size == len(want)
+    assert rejected > 100
+
+
+def test_rejects_wrong_level_bound():
+    rng = np.random.default_rng(3)
+    blocks, lits = streamgen.random_tokens(rng, 400, 8)
+    s, _ = streamgen.build(blocks, lits, 400, block_log2=8, max_level=0)
+    if oracle.tokens(streamgen.build(blocks, lits, 400, block_log2=8)[0])["lvl"].max() > 0:
+        with pytest.raises(oracle.OracleError):
+            oracle.decode(s)
+
+
+# ---------------------------------------------------- generated workloads
+
+@pytest.mark.parametrize("kind", ["markov", "fastq", "wiki", "random"])
+@pytest.mark.parametrize("opts", [dict(), dict(flatten=1), dict(max_depth=8), dict(flatten=2)],
+                         ids=["plain", "flat", "d8", "flatlit"])
+def test_generated_workloads(kind, opts):
+    n = 3 << 20
+    x = synth.make(kind, n, 0xACE0)
+    s = oracle.encode(x, block_log2=18, **opts)
+    rep = oracle.check(x, s)
+    assert rep.level_mismatch == 0
+    if opts.get("flatten") == 1:
+        assert rep.inblock_nonliteral_src_bytes == 0
+    if opts.get("max_depth"):
+        assert rep.depth_violations == 0 and rep.max_level <= 7
+    assert (oracle.decode_mt(s, 4) == x).all()
+    assert oracle.header_fields(s)["content_hash"] == oracle.content_hash(x)
