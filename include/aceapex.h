@@ -1,0 +1,143 @@
+/*
+ * aceapex.h -- C ABI of the MI355X (gfx950) decoder for absolute-offset LZ77
+ * streams (ACEAPEX, arXiv 2606.04268).
+ *
+ * What is decoded.  Every back-reference of the stream names an absolute
+ * byte position of the decoded output rather than a backward distance
+ * (Sec. 3.1), so a copy only needs its source bytes to be final.  The output
+ * is cut into self-contained blocks of 2^block_log2 bytes (Sec. 3.1).  Each
+ * block stores the four streams of Sec. 3.2 -- raw literals lit[], match
+ * lengths len[], absolute sources off[], and the command sequence cmd[]
+ * (literal-run lengths, one before each match plus a trailing run) -- plus
+ * lvl[], the dependency level of every match (Sec. 7.1: 0 when every source
+ * byte is a literal, else 1 + the highest level among the matches that wrote
+ * its source bytes), and a chunk index that lets a block be split into
+ * independently parsed pieces of 2^chunk_log2 sequences.
+ *
+ * How it is decoded on the GPU.  Literal runs are scattered to their output
+ * positions in parallel, then the matches execute level by level: all level-k
+ * copies are mutually independent, and level k only reads bytes written by
+ * literals or by levels < k (Sec. 7.1, the wavefront schedule of Sec. 7.1 and
+ * Sec. 7.4).  The decoder trusts lvl[] for ordering; a stream whose levels
+ * violate the definition decodes to unspecified bytes (never out of bounds).
+ *
+ * Stream layout (all integers little-endian):
+ *   header, 64 bytes:
+ *      0 char[4] "ACX1"        4 u16 version (1)      6 u16 flags
+ *      8 u8 block_log2          9 u8 min_match        10 u8 chunk_log2   11 u8 0
+ *     12 u32 max_depth (0 = unlimited)                 16 u64 decoded_bytes
+ *     24 u64 comp_bytes (whole stream)                 32 u32 n_blocks
+ *     36 u32 max_level         40 u32 n_seq (matches) 44 u32 n_deep (level >= 1)
+ *     48 u32 n_chunks          52 u32 0               56 u64 content hash (XXH3-64, 0 = absent)
+ *   block table at 64: (n_blocks + 1) x {u64 offset, u32 seq_base, u32 chunk_base};
+ *     entry n_blocks is {comp_bytes, n_seq, n_chunks}; offsets are 16-aligned
+ *   block payload: {u32 n_seq, n_lit, n_chunks, max_level, cmd_bytes,
+ *     len_bytes, lvl_bytes, 0}, then n_chunks x {u32 cmd_off, len_off,
+ *     lvl_off, lit_off, dst_off, 0, 0, 0}, then off[n_seq] (u32), cmd[]
+ *     (n_seq + 1 LEB128 runs), len[] (n_seq LEB128 values of length -
+ *     min_match), lvl[] (n_seq LEB128), lit[n_lit]; every section zero-padded
+ *     to a multiple of 16 bytes.  Every LEB128 value is at most 4 bytes long.
+ *   flags: bit0 flattened within blocks (Sec. 3.3), bit1 flattened along
+ *     literal-rooted chains only, bit2 depth-limited (Sec. 7.4), bit3 levels
+ *     present (always set).
+ *
+ * Conventions.  All pointers named d_* are device pointers on the current HIP
+ * device; h_* are host pointers.  The caller owns every buffer.  Calls that
+ * take a hip_stream (a hipStream_t, NULL = the null stream) enqueue work and
+ * return at once; problems the host can see are returned synchronously,
+ * problems found on the device are written to *d_status (0 = success) and
+ * are readable after the stream has been synchronised.  When the status is
+ * nonzero the output bytes are unspecified, but no write ever leaves
+ * [d_out, d_out + decoded_bytes) and no read leaves the compressed buffer or
+ * the output.  The library allocates no device memory on these paths.
+ *
+ * GPU limits of this version: decoded_bytes and comp_bytes below 2^32,
+ * 3 <= block_log2 <= 20, chunk_log2 <= 10, min_match >= 1.
+ */
+#ifndef ACEAPEX_H
+#define ACEAPEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ACEAPEX_OK 0
+#define ACEAPEX_E_INVAL -1       /* null pointer, misaligned buffer, bad argument          */
+#define ACEAPEX_E_FORMAT -2      /* bad magic / version / flags, inconsistent header       */
+#define ACEAPEX_E_CORRUPT -3     /* inconsistency found while parsing (device status)      */
+#define ACEAPEX_E_CAPACITY -4    /* out_capacity < decoded_bytes                           */
+#define ACEAPEX_E_WORKSPACE -5   /* workspace missing or too small                         */
+#define ACEAPEX_E_UNSUPPORTED -6 /* outside the GPU limits listed above                    */
+#define ACEAPEX_E_TIMEOUT -7     /* a device-side wait hit its spin limit (device status)  */
+#define ACEAPEX_E_HIP -8         /* HIP runtime error, see aceapex_last_hip_error()        */
+
+/* Header fields, filled on the host by aceapex_probe from a host copy of the
+ * first 64 bytes of the stream. */
+typedef struct {
+    uint64_t decoded_bytes; /* N: bytes the stream decodes to                       */
+    uint64_t comp_bytes;    /* size of the whole compressed stream                  */
+    uint32_t n_blocks;      /* ceil(N / 2^block_log2)                               */
+    uint32_t block_log2;
+    uint32_t min_match;
+    uint32_t chunk_log2;
+    uint32_t max_depth;     /* encoder depth limit, 0 = unlimited (Sec. 7.4)        */
+    uint32_t max_level;     /* highest match level; levels run 0..max_level         */
+    uint32_t flags;
+    uint32_t n_seq;         /* matches in the stream                                */
+    uint32_t n_deep;        /* matches with level >= 1                              */
+    uint32_t n_chunks;      /* chunk-index entries over all blocks                  */
+    uint64_t content_hash;  /* XXH3-64 of the decoded bytes, 0 if absent            */
+} aceapex_info;
+
+/* One compressed stream resident on the device. */
+typedef struct {
+    const void *d_comp;     /* device, caller-owned, comp_bytes long, 16-byte aligned */
+    aceapex_info info;      /* from aceapex_probe on the same bytes                   */
+} aceapex_stream;
+
+/* Per-stream descriptor of the batched call. */
+typedef struct {
+    aceapex_stream s;
+    void *d_out;            /* device, caller-owned, >= out_capacity bytes, 16-byte aligned */
+    uint64_t out_capacity;
+    int32_t *d_status;      /* device int32 written by the decoder (0 = ok); may be NULL   */
+} aceapex_desc;
+
+/* Parse and check the 64-byte header.  h_len must be >= 64.  Pure host code.
+ * Returns ACEAPEX_OK, ACEAPEX_E_INVAL (null pointer or h_len < 64) or
+ * ACEAPEX_E_FORMAT. */
+int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info);
+
+/* Device workspace, in bytes, that aceapex_decode_many needs for these n
+ * descriptors (n = 1 for aceapex_decode).  Pure host code; returns 0 when a
+ * descriptor's info is inconsistent. */
+size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n);
+
+/* Decode one stream into d_out (Sec. 3.2, Sec. 7.1).  d_workspace must hold
+ * aceapex_workspace_bytes() for this stream, 256-byte aligned; its contents
+ * on entry do not matter.  d_status may be NULL (the status is then kept in
+ * the workspace).  Asynchronous on hip_stream. */
+int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capacity,
+                   void *d_workspace, size_t ws_bytes, int32_t *d_status, void *hip_stream);
+
+/* Decode n independent streams (Sec. 7.5: blocks and streams are independent)
+ * as one batch on hip_stream.  h_descs is a host array; the workspace must
+ * hold aceapex_workspace_bytes(h_descs, n).  Returns the first synchronous
+ * error; per-stream device errors go to each d_status. */
+int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace,
+                        size_t ws_bytes, void *hip_stream);
+
+/* Static English text for an error code. */
+const char *aceapex_strerror(int code);
+
+/* The last hipError_t seen by a call that returned ACEAPEX_E_HIP (0 if none). */
+int aceapex_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACEAPEX_H */

@@ -1,0 +1,112 @@
+"""MI355X-native decoder for absolute-offset LZ77 streams (ACEAPEX, arXiv 2606.04268).
+
+Every step of a decode runs in the HIP kernels of ``libaceapex.so`` behind the
+C ABI of ``include/aceapex.h``; this module only moves arguments across it.
+PyTorch supplies device memory and streams.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import AceapexError, Info
+
+__all__ = ["AceapexError", "Info", "DeviceStream", "probe", "to_device", "workspace_bytes",
+           "decode", "decode_many", "check_status"]
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("the ACEAPEX decoder needs a ROCm GPU; none is visible")
+    return torch
+
+
+def probe(stream) -> Info:
+    """Header fields of a host-resident stream (aceapex_probe)."""
+    return _abi.probe(stream)
+
+
+@dataclass
+class DeviceStream:
+    """A compressed stream resident in device memory plus its probed header."""
+    comp: "object"  # torch.Tensor, uint8, on the GPU
+    info: Info
+
+    @property
+    def n(self) -> int:
+        return int(self.info.decoded_bytes)
+
+    def abi(self) -> _abi.Stream:
+        return _abi.Stream(self.comp.data_ptr(), self.info)
+
+
+def to_device(stream, device="cuda") -> DeviceStream:
+    """Copy a host stream (uint8 numpy array or bytes) to the GPU."""
+    torch = _torch()
+    host = np.ascontiguousarray(np.frombuffer(bytes(stream), np.uint8) if not isinstance(stream, np.ndarray)
+                                else stream, dtype=np.uint8)
+    info = probe(host)
+    if info.comp_bytes != host.size:
+        raise AceapexError(_abi.E_FORMAT, f"header says {info.comp_bytes} bytes, buffer has {host.size}")
+    comp = torch.from_numpy(host).to(device)
+    return DeviceStream(comp, info)
+
+
+def workspace_bytes(streams) -> int:
+    descs = [_abi.Desc(s.abi(), None, s.n, None) for s in streams]
+    return _abi.workspace_bytes(descs)
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return st.cuda_stream
+
+
+def decode(ds: DeviceStream, out=None, workspace=None, status=None, stream=None):
+    """Enqueue a decode of ``ds``; returns (out, status) tensors.  Asynchronous."""
+    torch = _torch()
+    dev = ds.comp.device
+    if out is None:
+        out = torch.empty(max(ds.n, 1), dtype=torch.uint8, device=dev)
+    need = workspace_bytes([ds])
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+    rc = _abi.decode(ds.abi(), out.data_ptr(), out.numel(), workspace.data_ptr(), workspace.numel(),
+                     status.data_ptr(), _stream_handle(stream))
+    if rc:
+        raise AceapexError(rc, "decode")
+    return out, status
+
+
+def decode_many(streams, outs=None, workspace=None, statuses=None, stream=None):
+    """Enqueue one batched decode of many streams; returns (outs, statuses)."""
+    torch = _torch()
+    dev = streams[0].comp.device if streams else "cuda"
+    if outs is None:
+        outs = [torch.empty(max(s.n, 1), dtype=torch.uint8, device=dev) for s in streams]
+    if statuses is None:
+        statuses = torch.empty(max(len(streams), 1), dtype=torch.int32, device=dev)
+    descs = [_abi.Desc(s.abi(), o.data_ptr(), o.numel(), statuses.data_ptr() + 4 * i)
+             for i, (s, o) in enumerate(zip(streams, outs))]
+    need = _abi.workspace_bytes(descs) if descs else 0
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    rc = _abi.decode_many(descs, workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
+    if rc:
+        raise AceapexError(rc, "decode_many")
+    return outs, statuses
+
+
+def check_status(status) -> None:
+    """Raise if any device status word is nonzero (synchronises)."""
+    vals = status.cpu().numpy().ravel()
+    bad = np.nonzero(vals)[0]
+    if bad.size:
+        raise AceapexError(int(vals[bad[0]]), f"device status of stream {int(bad[0])}")

@@ -1,0 +1,90 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol, and the host-side calls (probe, workspace sizing, argument checks)
+behave as include/aceapex.h states.  No compute call is made."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2606_04268_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "aceapex.h")).read()
+    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(aceapex_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.load()
+    names = declared_functions()
+    assert set(names) == set(_abi.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_probe_reads_header():
+    x = synth.markov(300_000, 3)
+    s = oracle.encode(x, block_log2=16, flatten=1)
+    info = _abi.probe(s)
+    h = oracle.header_fields(s)
+    assert info.decoded_bytes == len(x) == h["decoded_bytes"]
+    assert info.comp_bytes == s.size
+    for k in ("n_blocks", "max_level", "n_seq", "n_deep", "n_chunks", "flags", "block_log2",
+              "min_match", "chunk_log2", "max_depth", "content_hash"):
+        assert getattr(info, k) == h[k], k
+
+
+def test_probe_rejects_bad_headers():
+    s = oracle.encode(b"hello world hello world", block_log2=10)
+    with pytest.raises(_abi.AceapexError) as e:
+        _abi.probe(s[:10])
+    assert e.value.code == _abi.E_INVAL
+    for i, v in [(0, ord("B")), (4, 2), (7, 0x80), (6, 0), (11, 1), (32, 99)]:
+        bad = s.copy()
+        bad[i] = v
+        with pytest.raises(_abi.AceapexError) as e:
+            _abi.probe(bad)
+        assert e.value.code == _abi.E_FORMAT, i
+
+
+def test_workspace_bytes_scales_with_deep_matches():
+    x = synth.markov(1 << 20, 4)
+    a = oracle.encode(x, block_log2=18)
+    b = oracle.encode(x, block_log2=18, max_depth=1)
+    ia, ib = _abi.probe(a), _abi.probe(b)
+    wa = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia), 0, ia.decoded_bytes, 0)])
+    wb = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ib), 0, ib.decoded_bytes, 0)])
+    assert ib.n_deep == 0 and ia.n_deep > 0
+    assert wa - wb >= 12 * ia.n_deep
+    two = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia), 0, 0, 0)] * 2)
+    assert two == 2 * wa
+
+
+def test_host_argument_errors_need_no_gpu():
+    s = oracle.encode(synth.markov(5000, 1), block_log2=12)
+    info = _abi.probe(s)
+    lib = _abi.load()
+    st = _abi.Stream(0, info)
+    # null compressed pointer
+    assert lib.aceapex_decode(ctypes.byref(st), 4096, info.decoded_bytes, 4096, 1 << 20, None, None) == _abi.E_INVAL
+    st = _abi.Stream(16, info)
+    # output too small
+    assert lib.aceapex_decode(ctypes.byref(st), 4096, info.decoded_bytes - 1, 4096, 1 << 20, None, None) == _abi.E_CAPACITY
+    # misaligned output
+    assert lib.aceapex_decode(ctypes.byref(st), 4097, info.decoded_bytes, 4096, 1 << 20, None, None) == _abi.E_INVAL
+    # workspace too small / misaligned
+    assert lib.aceapex_decode(ctypes.byref(st), 4096, info.decoded_bytes, 4096, 16, None, None) == _abi.E_WORKSPACE
+    assert lib.aceapex_decode(ctypes.byref(st), 4096, info.decoded_bytes, 4100, 1 << 20, None, None) == _abi.E_WORKSPACE
+    # outside the GPU limits: 2^21-byte blocks
+    big = oracle.encode(synth.markov(5000, 1), block_log2=21)
+    ib = _abi.probe(big)
+    sb = _abi.Stream(16, ib)
+    assert lib.aceapex_decode(ctypes.byref(sb), 4096, ib.decoded_bytes, 4096, 1 << 20, None, None) == _abi.E_UNSUPPORTED
+    assert _abi.strerror(_abi.E_CORRUPT) == "corrupt stream"
+    assert lib.aceapex_decode_many(None, 0, None, 0, None) == _abi.OK

@@ -1,0 +1,159 @@
+"""GPU parity: every decode through the C ABI must equal, byte for byte, both
+the original bytes and the oracle's sequential decode of the same stream.
+Streams come from the oracle encoder or are hand-built token lists; no
+expected value comes from the GPU path."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import streamgen
+import synth
+from gpu_util import gpu_decode, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def parity(x, s, label):
+    say(f"[gpu] {label}: n={len(x)} comp={s.size} max_level={oracle.header_fields(s)['max_level']}")
+    got, status = gpu_decode(s)
+    assert status == 0, f"device status {status}"
+    want = np.frombuffer(bytes(x), np.uint8) if not isinstance(x, np.ndarray) else x
+    ref = oracle.decode(s)
+    assert np.array_equal(ref, want)
+    if not np.array_equal(got, want):
+        bad = np.nonzero(got != want)[0]
+        raise AssertionError(f"{bad.size} bytes differ, first at {bad[0]}")
+    return got
+
+
+def test_single_hip_runtime_in_process():
+    import torch
+
+    import paper_2606_04268_amd as ax
+    from paper_2606_04268_amd import _abi
+
+    _abi.load()
+    torch.zeros(1, device="cuda")
+    maps = open("/proc/self/maps").read()
+    libs = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(libs) == 1, libs
+    assert any(_abi.LIB_PATH in line for line in maps.splitlines())
+    assert ax is not None
+
+
+def test_config0_markov_4mib():
+    """The 4 MB text workload: order-2 Markov text with 20% copies, 1 MB
+    blocks, minimum match 4, no flattening."""
+    x = synth.markov(4 << 20, synth.CFG_SEEDS[0])
+    s = oracle.encode(x)
+    got = parity(x, s, "cfg0")
+    assert oracle.content_hash(got) == oracle.header_fields(s)["content_hash"]
+
+
+@pytest.mark.parametrize("kind", ["markov", "fastq", "wiki", "random"])
+@pytest.mark.parametrize("opts", [dict(), dict(flatten=1), dict(max_depth=8), dict(flatten=2),
+                                  dict(tiebreak=1)],
+                         ids=["plain", "flat", "d8", "flatlit", "recent"])
+def test_generated_kinds(kind, opts):
+    x = synth.make(kind, 3 << 19, 0xACE0 + len(kind))
+    s = oracle.encode(x, block_log2=18, **opts)
+    parity(x, s, f"{kind}/{opts}")
+
+
+@pytest.mark.parametrize("chunk_log2", [0, 3, 7, 10])
+@pytest.mark.parametrize("block_log2", [3, 9, 16, 20])
+def test_block_and_chunk_sizes(block_log2, chunk_log2):
+    x = synth.markov(200_000 + 1234, 77)
+    s = oracle.encode(x, block_log2=block_log2, chunk_log2=chunk_log2, hash_bits=16)
+    parity(x, s, f"bl{block_log2}/ck{chunk_log2}")
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_token_streams(seed):
+    rng = np.random.default_rng(100 + seed)
+    bl = [3, 4, 6, 10, 14, 20][seed % 6]
+    n = int(rng.integers(1, 60_000))
+    blocks, lits = streamgen.random_tokens(rng, n, bl, max_len=[5, 40, 700][seed % 3],
+                                           p_match=[0.3, 0.6, 0.9][seed % 3])
+    s, want = streamgen.build(blocks, lits, n, block_log2=bl, chunk_log2=int(rng.integers(0, 11)))
+    parity(np.frombuffer(want, np.uint8), s, f"tokens seed={seed} bl={bl}")
+
+
+def test_doubling_string_long_matches():
+    u = np.random.default_rng(7).permutation(256)[:16].astype(np.uint8).tobytes()
+    x = u * (1 << 16)  # 1 MiB of one repeated 16-byte unit: long matches, deep levels
+    s = oracle.encode(x, hash_bits=12)
+    parity(np.frombuffer(x, np.uint8), s, "doubling")
+
+
+def test_level_chain_beyond_lds_histogram():
+    """2000 chained 4-byte copies: levels 0..1999, past the per-workgroup
+    level histogram, so the deep levels take the global-atomic path."""
+    m = 2000
+    blocks = [([(4, 4, 0)] + [(0, 4, 4 * i) for i in range(1, m)], 0)]
+    n = 4 + 4 * m
+    s, want = streamgen.build(blocks, b"abcd", n, block_log2=14, chunk_log2=5)
+    assert oracle.header_fields(s)["max_level"] == m - 1
+    parity(np.frombuffer(want, np.uint8), s, "chain2000")
+
+
+def test_edge_cases():
+    for x in [b"", b"a", b"abc", b"abcd" * 3, bytes(range(256)), b"z" * 70_000]:
+        for o in [dict(), dict(block_log2=3, chunk_log2=0), dict(flatten=1, block_log2=4)]:
+            s = oracle.encode(x, hash_bits=10, **o)
+            parity(np.frombuffer(x, np.uint8), s, f"edge n={len(x)} {o}")
+
+
+def test_multiple_of_chunk_size():
+    blocks = [([(4, 4, 0)] * 8, 3)]
+    lits = bytes(range(35))
+    n = 8 * 8 + 3
+    s, want = streamgen.build(blocks, lits, n, block_log2=8, chunk_log2=2)
+    parity(np.frombuffer(want, np.uint8), s, "nseq%K==0")
+
+
+def test_decode_many_matches_single():
+    import torch
+
+    import paper_2606_04268_amd as ax
+
+    xs, ss = [], []
+    for i, kind in enumerate(["markov", "fastq", "random", "wiki", "markov"]):
+        x = synth.make(kind, 50_000 * (i + 1) + i, 500 + i)
+        xs.append(x)
+        ss.append(oracle.encode(x, block_log2=15, flatten=i % 2))
+    say("[gpu] decode_many x5")
+    dss = [ax.to_device(s) for s in ss]
+    outs, st = ax.decode_many(dss)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    for x, o in zip(xs, outs):
+        assert np.array_equal(o[: len(x)].cpu().numpy(), x)
+
+
+def test_stale_output_and_workspace_do_not_matter():
+    """Poisoned output and a dirty reused workspace give the same bytes."""
+    import torch
+
+    import paper_2606_04268_amd as ax
+
+    x = synth.fastq(1 << 20, 12)
+    s = oracle.encode(x, block_log2=17, flatten=1)
+    ds = ax.to_device(s)
+    ws = torch.full((ax.workspace_bytes([ds]),), 0x5A, dtype=torch.uint8, device="cuda")
+    for fill in (0x00, 0xFF, 0x3C):
+        out = torch.full((ds.n,), fill, dtype=torch.uint8, device="cuda")
+        say(f"[gpu] stale fill={fill:#x}")
+        ax.decode(ds, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), x)
