@@ -31,6 +31,8 @@
  *     48 u32 n_chunks          52 u32 0               56 u64 content hash (XXH3-64, 0 = absent)
  *   block table at 64: (n_blocks + 1) x {u64 offset, u32 seq_base, u32 chunk_base};
  *     entry n_blocks is {comp_bytes, n_seq, n_chunks}; offsets are 16-aligned
+ *   level table: (max_level + 1) x u32, the number of matches at each level,
+ *     zero-padded to a multiple of 16 bytes; the first block starts right after it
  *   block payload: {u32 n_seq, n_lit, n_chunks, max_level, cmd_bytes,
  *     len_bytes, lvl_bytes, 0}, then n_chunks x {u32 cmd_off, len_off,
  *     lvl_off, lit_off, dst_off, 0, 0, 0}, then off[n_seq] (u32), cmd[]
@@ -73,6 +75,7 @@ extern "C" {
 #define ACEAPEX_E_UNSUPPORTED -6 /* outside the GPU limits listed above                    */
 #define ACEAPEX_E_TIMEOUT -7     /* a device-side wait hit its spin limit (device status)  */
 #define ACEAPEX_E_HIP -8         /* HIP runtime error, see aceapex_last_hip_error()        */
+#define ACEAPEX_E_NOMEM -9       /* host allocation failed (encoder)                       */
 
 /* Header fields, filled on the host by aceapex_probe from a host copy of the
  * first 64 bytes of the stream. */
@@ -94,8 +97,13 @@ typedef struct {
 
 /* One compressed stream resident on the device. */
 typedef struct {
-    const void *d_comp;     /* device, caller-owned, comp_bytes long, 16-byte aligned */
-    aceapex_info info;      /* from aceapex_probe on the same bytes                   */
+    const void *d_comp;         /* device, caller-owned, comp_bytes long, 16-byte aligned    */
+    aceapex_info info;          /* from aceapex_probe on the same bytes                      */
+    const uint32_t *h_levels;   /* host copy of the level table (max_level + 1 counts, from  */
+                                /* aceapex_level_table), or NULL.  With it the wavefront is  */
+                                /* launched level by level at the size each level needs;     */
+                                /* without it every level gets a full-size launch.  Read     */
+                                /* during the decode call only.                              */
 } aceapex_stream;
 
 /* Per-stream descriptor of the batched call. */
@@ -110,6 +118,14 @@ typedef struct {
  * Returns ACEAPEX_OK, ACEAPEX_E_INVAL (null pointer or h_len < 64) or
  * ACEAPEX_E_FORMAT. */
 int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info);
+
+/* Copy the stream's level table (the number of matches at each dependency
+ * level 0..max_level, Sec. 7.1) from a host copy of the stream prefix of at
+ * least 64 + 16 * (n_blocks + 1) + 4 * (max_level + 1) bytes into counts[0, n),
+ * n >= max_level + 1.  Pure host code.  Returns ACEAPEX_OK, ACEAPEX_E_INVAL
+ * (null pointer, prefix or n too short) or ACEAPEX_E_FORMAT (bad header, or
+ * counts that do not add up to n_seq). */
+int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *counts, uint32_t n);
 
 /* Device workspace, in bytes, that aceapex_decode_many needs for these n
  * descriptors (n = 1 for aceapex_decode).  Pure host code; returns 0 when a
@@ -135,6 +151,55 @@ const char *aceapex_strerror(int code);
 
 /* The last hipError_t seen by a call that returned ACEAPEX_E_HIP (0 if none). */
 int aceapex_last_hip_error(void);
+
+/* ------------------------------------------------------------ measurement */
+
+/* Kernel timing, for benchmarks.  aceapex_timing(1) clears the record and
+ * makes every following decode on the calling host thread bracket each of
+ * its kernels with HIP events on the decode's stream; aceapex_timing(0)
+ * stops recording.  Groups: 0 setup (block and chunk-index checks, level
+ * offsets), 1 parse (LEB128 decode, literal scatter, match records by
+ * level), 2 levels (the match wavefront).  The set of kernels a decode
+ * launches is an implementation detail and may change between versions. */
+int aceapex_timing(int enable);
+
+/* Wait for the last recorded event, then write, for groups 0..n-1, the summed
+ * duration in milliseconds (ms[i]) and the number of recorded decodes that
+ * launched the group (count[i]); clears the record.  Returns ACEAPEX_OK,
+ * ACEAPEX_E_INVAL or ACEAPEX_E_HIP. */
+int aceapex_timing_read(float *ms, uint32_t *count, uint32_t n);
+
+/* ------------------------------------------------------------ host encoder */
+
+/* Encoder parameters.  The parse is greedy over hash chains of 4-byte
+ * hashes; its back-references are absolute output positions (Sec. 3.1). */
+typedef struct {
+    uint32_t block_log2;  /* self-contained blocks of 2^block_log2 bytes (paper: 1 MB = 20)      */
+    uint32_t min_match;   /* shortest match, >= 4                                                 */
+    uint32_t flatten;     /* Sec. 3.3 chain flattening: 0 off; 1 trace every match byte back      */
+                          /* through earlier copies of its block to a literal or to the first     */
+                          /* position outside the block; 2 only along chains that end at a        */
+                          /* literal of the block                                                 */
+    uint32_t max_depth;   /* Sec. 7.4 depth limit D: every match level <= D - 1; 0 = unlimited   */
+    uint32_t chain_depth; /* hash-chain candidates examined per position (32)                     */
+    uint32_t hash_bits;   /* log2 of the hash table (22)                                          */
+    uint32_t tiebreak;    /* among candidates of equal length: 0 lowest level, 1 most recent      */
+    uint32_t chunk_log2;  /* sequences per chunk-index entry (10)                                 */
+    uint32_t threads;     /* host threads, 0 = all                                                */
+} aceapex_enc_opts;
+
+/* Fill *o with the defaults above.  Pure host code. */
+void aceapex_enc_defaults(aceapex_enc_opts *o);
+
+/* Encode h_in[0, n) (host memory) into a stream in the layout above, with
+ * content hash 0.  On success *h_stream points to a malloc'd buffer owned by
+ * the caller (release with aceapex_free) and the stream length is returned;
+ * on failure a negative ACEAPEX_E_* code is returned and *h_stream is NULL.
+ * Pure host code; n must be below 2^32. */
+int64_t aceapex_encode(const void *h_in, uint64_t n, const aceapex_enc_opts *opts, void **h_stream);
+
+/* Release a buffer returned by aceapex_encode. */
+void aceapex_free(void *h_stream);
 
 #ifdef __cplusplus
 }

@@ -313,6 +313,8 @@ static void relevel_block(enc_t *e, uint64_t bs, uint64_t be, mvec_t *ms)
  *     u32 n_chunks, u32 0, u64 content_hash (0 = absent)
  *   block table: (n_blocks+1) x {u64 offset, u32 seq_base, u32 chunk_base};
  *     the last entry is {comp_bytes, n_seq, n_chunks}
+ *   level table: (max_level+1) x u32, the number of matches at each level,
+ *     zero-padded to a multiple of 16 bytes; the first block follows it
  *   per block, at its 16-aligned offset:
  *     header (32 B): u32 n_seq, n_lit, n_chunks, max_level, cmd_bytes,
  *       len_bytes, lvl_bytes, 0
@@ -323,9 +325,26 @@ static void relevel_block(enc_t *e, uint64_t bs, uint64_t be, mvec_t *ms)
  *     every section padded with zeros to a multiple of 16 bytes
  */
 typedef struct {
-    buf_t s;
+    buf_t s;          /* block payloads, offsets relative to the first block */
     uint32_t max_level, n_seq, n_deep, n_chunks;
+    uint32_t *hist;   /* matches per level */
+    uint64_t hist_cap;
+    int oom;
 } writer_t;
+
+static void count_level(writer_t *w, uint32_t lv)
+{
+    if (lv >= w->hist_cap) {
+        uint64_t nc = w->hist_cap ? w->hist_cap : 64;
+        while (nc <= lv) nc *= 2;
+        uint32_t *nh = realloc(w->hist, nc * sizeof(uint32_t));
+        if (!nh) { w->oom = 1; return; }
+        memset(nh + w->hist_cap, 0, (nc - w->hist_cap) * sizeof(uint32_t));
+        w->hist = nh;
+        w->hist_cap = nc;
+    }
+    w->hist[lv]++;
+}
 
 static int write_block(writer_t *w, const enc_t *e, uint64_t bs, uint64_t be, const mvec_t *ms,
                        uint64_t *tbl_seq_base, uint64_t *tbl_chunk_base)
@@ -357,6 +376,7 @@ static int write_block(writer_t *w, const enc_t *e, uint64_t bs, uint64_t be, co
             if ((uint32_t)m->lvl > blk_max) blk_max = (uint32_t)m->lvl;
             if ((uint32_t)m->lvl > w->max_level) w->max_level = (uint32_t)m->lvl;
             if (m->lvl > 0) w->n_deep++;
+            count_level(w, (uint32_t)m->lvl);
             x += m->len;
         }
     }
@@ -377,7 +397,7 @@ static int write_block(writer_t *w, const enc_t *e, uint64_t bs, uint64_t be, co
         buf_put(&w->s, secs[k]->p, secs[k]->len);
         buf_zero(&w->s, pad16(secs[k]->len) - secs[k]->len);
     }
-    int oom = cmd.oom | len.oom | lvl.oom | lit.oom | off.oom | w->s.oom;
+    int oom = cmd.oom | len.oom | lvl.oom | lit.oom | off.oom | w->s.oom | w->oom;
     free(cmd.p); free(len.p); free(lvl.p); free(lit.p); free(off.p); free(chunk);
     w->n_seq += (uint32_t)nseq;
     w->n_chunks += (uint32_t)nchunks;
@@ -405,12 +425,14 @@ int64_t orc_encode(const uint8_t *x, uint64_t n, const orc_opts *o, uint8_t **ou
     const uint64_t B = (uint64_t)1 << o->block_log2;
     const uint64_t nb = (n + B - 1) / B;
     uint64_t *tbl = calloc((nb + 1) * 3, sizeof(uint64_t));
-    writer_t w = {{0}, 0, 0, 0, 0};
+    writer_t w;
+    memset(&w, 0, sizeof w);
+    uint8_t *final = NULL;
+    uint64_t total = 0;
     int rc = ORC_OK;
     if (!e.head || !e.prev || !e.lvb || !tbl) { rc = ORC_E_NOMEM; goto done; }
     memset(e.head, 0xff, ((size_t)1 << o->hash_bits) * sizeof(uint32_t));
 
-    buf_zero(&w.s, HDR_BYTES + (nb + 1) * 16);
     for (uint64_t b = 0; b < nb; b++) {
         uint64_t bs = b * B, be = bs + B < n ? bs + B : n;
         mvec_t ms = {0};
@@ -423,11 +445,20 @@ int64_t orc_encode(const uint8_t *x, uint64_t n, const orc_opts *o, uint8_t **ou
         }
         free(ms.m);
     }
-    if (w.s.oom) { rc = ORC_E_NOMEM; goto done; }
-    tbl[nb * 3 + 0] = w.s.len;
+    if (w.s.oom || w.oom) { rc = ORC_E_NOMEM; goto done; }
+    const uint64_t hist_n = (uint64_t)w.max_level + 1;
+    const uint64_t prefix = HDR_BYTES + (nb + 1) * 16 + pad16(4 * hist_n);
+    total = prefix + w.s.len;
+    final = calloc(total, 1);
+    if (!final) { rc = ORC_E_NOMEM; goto done; }
+    if (w.s.len) memcpy(final + prefix, w.s.p, w.s.len);
+    for (uint64_t l = 0; l < hist_n; l++)
+        wr32(final + HDR_BYTES + (nb + 1) * 16 + 4 * l, l < w.hist_cap ? w.hist[l] : 0);
+    for (uint64_t b = 0; b < nb; b++) tbl[b * 3 + 0] += prefix;
+    tbl[nb * 3 + 0] = total;
     tbl[nb * 3 + 1] = w.n_seq;
     tbl[nb * 3 + 2] = w.n_chunks;
-    uint8_t *h = w.s.p;
+    uint8_t *h = final;
     memcpy(h, "ACX1", 4);
     wr16(h + 4, 1);
     uint16_t flags = FLAG_LEVELS;
@@ -440,7 +471,7 @@ int64_t orc_encode(const uint8_t *x, uint64_t n, const orc_opts *o, uint8_t **ou
     h[10] = (uint8_t)o->chunk_log2;
     wr32(h + 12, (uint32_t)o->max_depth);
     wr64(h + 16, n);
-    wr64(h + 24, w.s.len);
+    wr64(h + 24, total);
     wr32(h + 32, (uint32_t)nb);
     wr32(h + 36, w.max_level);
     wr32(h + 40, w.n_seq);
@@ -453,10 +484,10 @@ int64_t orc_encode(const uint8_t *x, uint64_t n, const orc_opts *o, uint8_t **ou
         wr32(t + 12, (uint32_t)tbl[b * 3 + 2]);
     }
 done:
-    free(e.head); free(e.prev); free(e.lvb); free(tbl);
-    if (rc != ORC_OK) { free(w.s.p); return rc; }
-    *out = w.s.p;
-    return (int64_t)w.s.len;
+    free(e.head); free(e.prev); free(e.lvb); free(tbl); free(w.s.p); free(w.hist);
+    if (rc != ORC_OK) { free(final); return rc; }
+    *out = final;
+    return (int64_t)total;
 }
 
 /* ------------------------------------------------------------ stream reader */
@@ -474,6 +505,12 @@ typedef struct {
     const uint8_t *chunks, *off, *cmd, *len, *lvl, *lit;
     uint64_t out_start, out_end;
 } sblk_t;
+
+/* header + block table + level table */
+static uint64_t prefix_bytes(const shdr_t *h)
+{
+    return HDR_BYTES + ((uint64_t)h->n_blocks + 1) * 16 + pad16(4 * ((uint64_t)h->max_level + 1));
+}
 
 static int read_header(const uint8_t *s, uint64_t slen, shdr_t *h)
 {
@@ -496,7 +533,8 @@ static int read_header(const uint8_t *s, uint64_t slen, shdr_t *h)
     uint64_t B = (uint64_t)1 << h->block_log2;
     if ((h->n + B - 1) / B != h->n_blocks) return ORC_E_FORMAT;
     if (h->comp != slen) return ORC_E_FORMAT;
-    if (HDR_BYTES + ((uint64_t)h->n_blocks + 1) * 16 > slen) return ORC_E_FORMAT;
+    if (h->max_level >= VARINT_LIMIT) return ORC_E_FORMAT;
+    if (prefix_bytes(h) > slen) return ORC_E_FORMAT;
     return ORC_OK;
 }
 
@@ -504,7 +542,7 @@ static int read_block(const uint8_t *s, const shdr_t *h, uint32_t b, sblk_t *k)
 {
     const uint8_t *t = s + HDR_BYTES + (uint64_t)b * 16;
     uint64_t o0 = rd64(t), o1 = rd64(t + 16);
-    if ((o0 & 15) || o1 < o0 || o1 > h->comp || o0 < HDR_BYTES + ((uint64_t)h->n_blocks + 1) * 16)
+    if ((o0 & 15) || o1 < o0 || o1 > h->comp || o0 < prefix_bytes(h))
         return ORC_E_FORMAT;
     if (o1 - o0 < BLK_HDR_BYTES) return ORC_E_CORRUPT;
     const uint8_t *p = s + o0;
@@ -539,7 +577,8 @@ static int check_table(const uint8_t *s, const shdr_t *h)
 {
     const uint8_t *last = s + HDR_BYTES + (uint64_t)h->n_blocks * 16;
     if (rd64(last) != h->comp || rd32(last + 8) != h->n_seq || rd32(last + 12) != h->n_chunks) return ORC_E_FORMAT;
-    if (h->n_blocks == 0 && (h->n_seq || h->n_chunks || h->comp != HDR_BYTES + 16)) return ORC_E_FORMAT;
+    if (h->n_blocks == 0 && (h->n_seq || h->n_chunks || h->comp != prefix_bytes(h))) return ORC_E_FORMAT;
+    if (h->n_blocks && rd64(s + HDR_BYTES) != prefix_bytes(h)) return ORC_E_FORMAT;
     if (h->n_blocks && rd32(s + HDR_BYTES + 8) != 0) return ORC_E_FORMAT;
     if (h->n_blocks && rd32(s + HDR_BYTES + 12) != 0) return ORC_E_FORMAT;
     return ORC_OK;
@@ -558,6 +597,7 @@ typedef struct {
     uint64_t tok_cap, tok_n;
     uint32_t max_level;
     uint64_t n_deep;
+    uint64_t *level_count; /* [max_level + 1] matches seen per level, may be NULL */
     /* for the multi-threaded decoder */
     _Atomic uint64_t *progress;
     uint64_t B;
@@ -612,6 +652,7 @@ static int run_block(const shdr_t *h, const sblk_t *k, exec_t *x, uint32_t b)
         }
         if (lv > x->max_level) x->max_level = lv;
         if (lv > 0) x->n_deep++;
+        if (x->level_count) x->level_count[lv]++;
         p += m;
         if (x->progress) atomic_store_explicit(&x->progress[b], p - k->out_start, memory_order_release);
     }
@@ -629,15 +670,25 @@ static int decode_all(const uint8_t *s, uint64_t slen, exec_t *x, uint64_t cap, 
     if (n_out) *n_out = h.n;
     if (cap < h.n) return ORC_E_CAPACITY;
     uint64_t seqs = 0;
-    for (uint32_t b = 0; b < h.n_blocks; b++) {
+    uint64_t *cnt = calloc((uint64_t)h.max_level + 1, sizeof(uint64_t));
+    if (!cnt) return ORC_E_NOMEM;
+    x->level_count = cnt;
+    for (uint32_t b = 0; b < h.n_blocks && !rc; b++) {
         sblk_t k;
-        if ((rc = read_block(s, &h, b, &k))) return rc;
-        if ((rc = run_block(&h, &k, x, b))) return rc;
+        if ((rc = read_block(s, &h, b, &k))) break;
+        if ((rc = run_block(&h, &k, x, b))) break;
         seqs += k.n_seq;
     }
-    if (seqs != h.n_seq || x->n_deep != h.n_deep) return ORC_E_CORRUPT;
-    if (x->max_level != h.max_level) return ORC_E_CORRUPT;
-    return ORC_OK;
+    x->level_count = NULL;
+    if (!rc && (seqs != h.n_seq || x->n_deep != h.n_deep || x->max_level != h.max_level)) rc = ORC_E_CORRUPT;
+    /* the level table must count exactly the matches of every level */
+    const uint8_t *lt = s + HDR_BYTES + ((uint64_t)h.n_blocks + 1) * 16;
+    for (uint64_t l = 0; !rc && l <= h.max_level; l++)
+        if (rd32(lt + 4 * l) != cnt[l]) rc = ORC_E_CORRUPT;
+    for (uint64_t q = 4 * ((uint64_t)h.max_level + 1); !rc && q < pad16(4 * ((uint64_t)h.max_level + 1)); q++)
+        if (lt[q]) rc = ORC_E_CORRUPT;
+    free(cnt);
+    return rc;
 }
 
 /* sequential decode; the output is the definition of the decoded result */

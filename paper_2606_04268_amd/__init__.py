@@ -13,8 +13,8 @@ import numpy as np
 from . import _abi
 from ._abi import AceapexError, Info
 
-__all__ = ["AceapexError", "Info", "DeviceStream", "probe", "to_device", "workspace_bytes",
-           "decode", "decode_many", "check_status"]
+__all__ = ["AceapexError", "Info", "DeviceStream", "probe", "encode", "to_device",
+           "workspace_bytes", "decode", "decode_many", "check_status", "content_hash"]
 
 
 def _torch():
@@ -25,6 +25,31 @@ def _torch():
     return torch
 
 
+def content_hash(data) -> int:
+    """XXH3-64 of a host buffer, the verification hash of Sec. 4.3 (xxhash package)."""
+    import xxhash
+
+    return xxhash.xxh3_64_intdigest(memoryview(np.ascontiguousarray(data, dtype=np.uint8)))
+
+
+def encode(data, *, with_hash: bool = True, **opts) -> np.ndarray:
+    """Encode host bytes into a stream (host encoder in libaceapex.so).
+
+    Options (see aceapex_enc_opts): block_log2, min_match, flatten, max_depth,
+    chain_depth, hash_bits, tiebreak, chunk_log2, threads.
+    """
+    o = _abi.enc_defaults()
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown encoder option {k}")
+        setattr(o, k, int(v))
+    s = _abi.encode(data, o)
+    x = np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray) else data
+    if with_hash and x.size:
+        s[56:64] = np.frombuffer(content_hash(x).to_bytes(8, "little"), dtype=np.uint8)
+    return s
+
+
 def probe(stream) -> Info:
     """Header fields of a host-resident stream (aceapex_probe)."""
     return _abi.probe(stream)
@@ -32,16 +57,18 @@ def probe(stream) -> Info:
 
 @dataclass
 class DeviceStream:
-    """A compressed stream resident in device memory plus its probed header."""
+    """A compressed stream resident in device memory plus its probed header
+    and a host copy of its level table (matches per level)."""
     comp: "object"  # torch.Tensor, uint8, on the GPU
     info: Info
+    levels: "object" = None  # ctypes uint32 array, or None
 
     @property
     def n(self) -> int:
         return int(self.info.decoded_bytes)
 
     def abi(self) -> _abi.Stream:
-        return _abi.Stream(self.comp.data_ptr(), self.info)
+        return _abi.Stream(self.comp.data_ptr(), self.info, self.levels)
 
 
 def to_device(stream, device="cuda") -> DeviceStream:
@@ -52,8 +79,9 @@ def to_device(stream, device="cuda") -> DeviceStream:
     info = probe(host)
     if info.comp_bytes != host.size:
         raise AceapexError(_abi.E_FORMAT, f"header says {info.comp_bytes} bytes, buffer has {host.size}")
+    levels = _abi.level_table(host, info)
     comp = torch.from_numpy(host).to(device)
-    return DeviceStream(comp, info)
+    return DeviceStream(comp, info, levels)
 
 
 def workspace_bytes(streams) -> int:

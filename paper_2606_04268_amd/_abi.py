@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libaceapex.so")
 
 OK = 0
 E_INVAL, E_FORMAT, E_CORRUPT, E_CAPACITY = -1, -2, -3, -4
-E_WORKSPACE, E_UNSUPPORTED, E_TIMEOUT, E_HIP = -5, -6, -7, -8
+E_WORKSPACE, E_UNSUPPORTED, E_TIMEOUT, E_HIP, E_NOMEM = -5, -6, -7, -8, -9
 
 
 class Info(ctypes.Structure):
@@ -34,13 +34,20 @@ class Info(ctypes.Structure):
 
 class Stream(ctypes.Structure):
     """aceapex_stream."""
-    _fields_ = [("d_comp", ctypes.c_void_p), ("info", Info)]
+    _fields_ = [("d_comp", ctypes.c_void_p), ("info", Info), ("h_levels", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class Desc(ctypes.Structure):
     """aceapex_desc."""
     _fields_ = [("s", Stream), ("d_out", ctypes.c_void_p), ("out_capacity", ctypes.c_uint64),
                 ("d_status", ctypes.c_void_p)]
+
+
+class EncOpts(ctypes.Structure):
+    """aceapex_enc_opts."""
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "block_log2", "min_match", "flatten", "max_depth", "chain_depth", "hash_bits",
+        "tiebreak", "chunk_log2", "threads")]
 
 
 class AceapexError(RuntimeError):
@@ -50,8 +57,11 @@ class AceapexError(RuntimeError):
         self.code = code
 
 
-EXPORTS = ("aceapex_probe", "aceapex_workspace_bytes", "aceapex_decode", "aceapex_decode_many",
-           "aceapex_strerror", "aceapex_last_hip_error")
+EXPORTS = ("aceapex_probe", "aceapex_level_table", "aceapex_workspace_bytes", "aceapex_decode", "aceapex_decode_many",
+           "aceapex_strerror", "aceapex_last_hip_error", "aceapex_enc_defaults", "aceapex_encode",
+           "aceapex_free", "aceapex_timing", "aceapex_timing_read")
+
+PHASES = ("setup", "parse", "levels")
 
 _lib = None
 
@@ -71,6 +81,8 @@ def load():
     vp = ctypes.c_void_p
     lib.aceapex_probe.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(Info)]
     lib.aceapex_probe.restype = ctypes.c_int
+    lib.aceapex_level_table.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32]
+    lib.aceapex_level_table.restype = ctypes.c_int
     lib.aceapex_workspace_bytes.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint32]
     lib.aceapex_workspace_bytes.restype = ctypes.c_size_t
     lib.aceapex_decode.argtypes = [ctypes.POINTER(Stream), vp, ctypes.c_uint64, vp, ctypes.c_size_t, vp, vp]
@@ -81,6 +93,17 @@ def load():
     lib.aceapex_strerror.restype = ctypes.c_char_p
     lib.aceapex_last_hip_error.argtypes = []
     lib.aceapex_last_hip_error.restype = ctypes.c_int
+    lib.aceapex_enc_defaults.argtypes = [ctypes.POINTER(EncOpts)]
+    lib.aceapex_enc_defaults.restype = None
+    lib.aceapex_encode.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(EncOpts), ctypes.POINTER(vp)]
+    lib.aceapex_encode.restype = ctypes.c_int64
+    lib.aceapex_free.argtypes = [vp]
+    lib.aceapex_free.restype = None
+    lib.aceapex_timing.argtypes = [ctypes.c_int]
+    lib.aceapex_timing.restype = ctypes.c_int
+    lib.aceapex_timing_read.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.c_uint32]
+    lib.aceapex_timing_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -101,6 +124,19 @@ def probe(prefix) -> Info:
     return info
 
 
+def level_table(stream, info: Info):
+    """aceapex_level_table on a host stream: a ctypes uint32 array of max_level + 1 counts."""
+    import numpy as np
+
+    buf = np.ascontiguousarray(stream, dtype=np.uint8)
+    n = info.max_level + 1
+    counts = (ctypes.c_uint32 * n)()
+    rc = load().aceapex_level_table(buf.ctypes.data, buf.size, counts, n)
+    if rc:
+        raise AceapexError(rc, "level_table")
+    return counts
+
+
 def workspace_bytes(descs) -> int:
     arr = (Desc * len(descs))(*descs)
     return int(load().aceapex_workspace_bytes(arr, len(descs)))
@@ -115,3 +151,41 @@ def decode(stream: Stream, d_out: int, out_capacity: int, d_ws: int, ws_bytes: i
 def decode_many(descs, d_ws: int, ws_bytes: int, hip_stream: int) -> int:
     arr = (Desc * len(descs))(*descs)
     return load().aceapex_decode_many(arr, len(descs), d_ws, ws_bytes, hip_stream)
+
+
+def enc_defaults() -> EncOpts:
+    o = EncOpts()
+    load().aceapex_enc_defaults(ctypes.byref(o))
+    return o
+
+
+def encode(data, opts: EncOpts):
+    """aceapex_encode on a host buffer; returns the stream as a uint8 numpy array."""
+    import numpy as np
+
+    x = np.ascontiguousarray(np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray)
+                             else data, dtype=np.uint8)
+    out = ctypes.c_void_p()
+    n = load().aceapex_encode(x.ctypes.data if x.size else None, x.size, ctypes.byref(opts), ctypes.byref(out))
+    if n < 0:
+        raise AceapexError(int(n), "encode")
+    try:
+        s = np.ctypeslib.as_array(ctypes.cast(out, ctypes.POINTER(ctypes.c_uint8)), shape=(n,)).copy()
+    finally:
+        load().aceapex_free(out)
+    return s
+
+
+def timing(enable: bool) -> None:
+    load().aceapex_timing(1 if enable else 0)
+
+
+def timing_read():
+    """{group name: (total ms, launches)} of the decodes recorded since timing(True)."""
+    n = len(PHASES)
+    ms = (ctypes.c_float * n)()
+    cnt = (ctypes.c_uint32 * n)()
+    rc = load().aceapex_timing_read(ms, cnt, n)
+    if rc:
+        raise AceapexError(rc, "timing_read")
+    return {PHASES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}

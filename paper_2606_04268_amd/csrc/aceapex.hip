@@ -1,40 +1,54 @@
 // MI355X (gfx950) decoder for absolute-offset LZ77 streams (ACEAPEX,
 // arXiv 2606.04268) behind the C ABI of include/aceapex.h.
 //
-// Pipeline for one stream (all on one HIP stream, no host round trip):
-//   k_init     clear level counters, status and the chunk descriptors
-//   k_setup    one workgroup per block: check the block table, block header
-//              and chunk index, and write a 48-byte descriptor per chunk
-//              (absolute slices of cmd/len/lvl/lit/off and the output span)
-//   k_phase1   one workgroup per chunk: LEB128-decode cmd/len/lvl from LDS,
-//              prefix-scan run and match lengths into output and literal
-//              offsets, scatter the literal runs (Sec. 3.2) and count the
-//              matches of every level >= 1
-//   k_lscan    prefix over the level histogram -> bucket bases
-//   k_phase2   one workgroup per chunk: parse again, run every level-0 match
-//              at once (its source bytes are literals, already final), and
-//              append each deeper match to the bucket of its level
-//   k_level    for k = 1..max_level: run the bucket of level k.  Level k reads
-//              only bytes written by literals or by levels < k (Sec. 7.1), so
-//              the copies of one level are independent of each other.
+// A decode is a short sequence of launches on the caller's stream, with no
+// host round trip:
+//
+//   k_setup   one workgroup per block checks the block table, block header and
+//             chunk index and writes a 48-byte descriptor per chunk (absolute
+//             slices of cmd/len/lvl/lit/off and the output span).  Workgroup 0
+//             also turns the stream's level table (matches per level) into the
+//             first record of every level and clears the counters.
+//   k_parse   one workgroup per chunk, four sequences per thread.  When every
+//             cmd/len/lvl value of the chunk is one byte long (the slice length
+//             equals the value count) each thread reads its four values with a
+//             single 4-byte load per stream; otherwise three waves decode the
+//             LEB128 slices into LDS first.  A workgroup scan turns run and
+//             match lengths into output and literal offsets, each thread
+//             copies its literal runs to their places (Sec. 3.2), and every
+//             match becomes a 12-byte record (dst, src, len) in the bucket of
+//             its level.
+//   k_level   one launch per level k (Sec. 7.1): the copies of level k read
+//             only bytes written by literals or by lower levels and are
+//             independent of each other, so every thread simply runs four
+//             records at a time.  Launch boundaries order the levels.
+//   k_tail    the deep levels that hold few matches run in a single workgroup,
+//             level after level, separated by workgroup barriers: one CU, so
+//             no cache maintenance between levels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
+
+#include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "aceapex.h"
 
 namespace {
 
 constexpr int NT = 256;                     // threads per workgroup
+constexpr int NT_TAIL = 1024;               // threads of the tail workgroup
 constexpr uint32_t K_LOG2_MAX = 10;         // sequences per chunk, at most
 constexpr uint32_t K_MAX = 1u << K_LOG2_MAX;
-constexpr uint32_t STAGE = 4 * (K_MAX + 1) + 12;  // one LEB128 slice, 4 bytes per value at most
-constexpr uint32_t STAGE_PAD = (STAGE + 15) & ~15u;
-constexpr uint32_t LVL_LDS = 1024;          // levels counted in LDS; deeper ones use global atomics
-constexpr uint32_t SKIP = 0xffffffffu;      // descriptor of a chunk that must not be executed
+constexpr uint32_t PER = K_MAX / NT;        // sequences per thread in k_parse
+constexpr uint32_t LH = 256;                // levels bucketed through LDS; deeper ones use global atomics
 constexpr uint32_t HDR = 64, BLKHDR = 32, CHUNK_ENT = 32;
 constexpr uint32_t BLOCK_LOG2_MAX = 20;
-constexpr int LEVEL_GRID = 1024;            // workgroups of a per-level launch
+constexpr uint32_t ROUND = 4;               // records per thread per round of k_level / k_tail
+constexpr uint32_t LONG_COPY = 128;         // matches longer than this are copied by a whole wave
+constexpr uint32_t LEVEL_WG_MAX = 2048;     // workgroups of one level launch, at most
+constexpr uint32_t TAIL_LEVEL_MAX = 8192;   // levels with at most this many matches may join the tail
 
 typedef uint16_t u16u __attribute__((aligned(1)));
 typedef uint32_t u32u __attribute__((aligned(1)));
@@ -57,23 +71,35 @@ struct Job {
     uint8_t *out;
     uint32_t n, comp_bytes;
     uint32_t n_blocks, block_log2, min_match, chunk_log2;
-    uint32_t max_level, n_chunks, n_seq, n_deep;
+    uint32_t max_level, n_chunks, n_seq;
     ChunkDesc *chunks;   // [n_chunks]
-    uint32_t *hist;      // [max_level + 1] deep matches per level
-    uint32_t *base;      // [max_level + 2] bucket starts
-    uint32_t *cursor;    // [max_level + 1] next free slot per bucket
-    uint32_t *recs;      // [3 * n_deep] (dst, src, len) of every deep match
+    uint8_t *blk_ok;     // [n_blocks] 1 when the block passed the checks of k_setup
+    uint32_t *rec_base;  // [max_level + 2] first record of each level
+    uint32_t *cursor;    // [max_level + 1] next free record of each level (without block cursors)
+    uint32_t *bcount;    // [(max_level + 1) * n_blocks] matches per (level, block)
+    uint32_t *bcursor;   // [(max_level + 1) * n_blocks] next free record per (level, block)
+    uint32_t use_bcur;   // records are reserved per (level, block) rather than per level
+    uint32_t *recs;      // [3 * n_seq] (dst, src, len)
     int32_t *status;
 };
+
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// their index.  xcd_slot maps the hardware index i of G workgroups to a
+// logical index such that every XCD receives one contiguous range, so that
+// neighbouring chunks and records -- and the cache lines they share -- stay
+// in one L2.
+__device__ __forceinline__ uint32_t xcd_slot(uint32_t i, uint32_t G)
+{
+    const uint32_t P = G < 8 ? G : 8;
+    const uint32_t x = i % P, k = i / P, q = G / P, r = G % P;
+    return x * q + min(x, r) + k;
+}
 
 __device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *(const u32u *)p; }
 __device__ __forceinline__ uint64_t ld64(const uint8_t *p) { return *(const u64u *)p; }
 __device__ __forceinline__ uint64_t pad16(uint64_t v) { return (v + 15) & ~(uint64_t)15; }
 
-__device__ __forceinline__ void fail(const Job &j, int code)
-{
-    atomicCAS(j.status, 0, code);
-}
+__device__ __forceinline__ void fail(const Job &j, int code) { atomicCAS(j.status, 0, code); }
 
 // Copy n bytes between non-overlapping ranges with unaligned 16/8/4/2/1-byte
 // accesses; every access touches exactly the bytes of the copy.
@@ -90,7 +116,101 @@ __device__ __forceinline__ void copy_bytes(uint8_t *d, const uint8_t *s, uint32_
     if (n & 1) *d = *s;
 }
 
-// ------------------------------------------------------------ workgroup scans
+// Store the first n (1..16) bytes of lo:hi at d with exact unaligned stores.
+__device__ __forceinline__ void store_upto16(uint8_t *d, uint64_t lo, uint64_t hi, uint32_t n)
+{
+    if (n >= 8) {
+        *(u64u *)d = lo;
+        d += 8;
+        lo = hi;
+        n -= 8;
+        if (n == 8) { *(u64u *)d = lo; return; }
+    }
+    if (n & 4) { *(u32u *)d = (uint32_t)lo; d += 4; lo >>= 32; }
+    if (n & 2) { *(u16u *)d = (uint16_t)lo; d += 2; lo >>= 16; }
+    if (n & 1) *d = (uint8_t)lo;
+}
+
+// Whole-wave copy of one long range: lane i moves the 16-byte pieces i, i+64, ...
+__device__ __forceinline__ void wave_copy(uint8_t *d, const uint8_t *s, uint32_t n)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t o = lane * 16; o < n; o += 64 * 16) copy_bytes(d + o, s + o, min(16u, n - o));
+}
+
+// Run up to ROUND match records held by this thread.  Matches of at most 16
+// bytes take one 16-byte load of their source (when 16 bytes are there to
+// read: bytes past the match are read and discarded) and exact stores; all
+// loads of the round are issued before the stores.  Longer matches are then
+// copied by the whole wave, one at a time.
+__device__ __forceinline__ void run_records(const Job &j, const uint32_t *dst, const uint32_t *src,
+                                            uint32_t *len, bool &bad)
+{
+    uint64_t lo[ROUND], hi[ROUND];
+#pragma unroll
+    for (uint32_t u = 0; u < ROUND; u++) {
+        if (len[u] && ((uint64_t)dst[u] + len[u] > j.n || (uint64_t)src[u] + len[u] > dst[u])) {
+            bad = true;
+            len[u] = 0;
+        }
+        const bool small = len[u] && len[u] <= 16 && (uint64_t)src[u] + 16 <= j.n;
+        const uint8_t *p = j.out + (small ? src[u] : 0u);
+        lo[u] = 0; hi[u] = 0;
+        if (small || j.n >= 16) {
+            lo[u] = ld64(p);
+            hi[u] = ld64(p + 8);
+        }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < ROUND; u++) {
+        if (!len[u]) continue;
+        if (len[u] <= 16 && (uint64_t)src[u] + 16 <= j.n) {
+            store_upto16(j.out + dst[u], lo[u], hi[u], len[u]);
+        } else if (len[u] <= LONG_COPY) {
+            copy_bytes(j.out + dst[u], j.out + src[u], len[u]);
+        }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < ROUND; u++) {
+        uint64_t m = __ballot(len[u] > LONG_COPY);
+        while (m) {
+            const int lane = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const uint32_t d0 = __shfl(dst[u], lane, 64), s0 = __shfl(src[u], lane, 64);
+            const uint32_t n0 = __shfl(len[u], lane, 64);
+            wave_copy(j.out + d0, j.out + s0, n0);
+        }
+    }
+}
+
+// Load ROUND records r0, r0 + stride, ... (those below r_end) without
+// waiting between them.
+__device__ __forceinline__ void load_records(const Job &j, uint32_t r0, uint32_t stride, uint32_t r_end,
+                                             uint32_t *dst, uint32_t *src, uint32_t *len)
+{
+#pragma unroll
+    for (uint32_t u = 0; u < ROUND; u++) {
+        const uint32_t i = r0 + u * stride;
+        const bool ok = i < r_end;
+        const uint32_t *r = j.recs + 3ull * (ok ? i : r0);
+        dst[u] = r[0];
+        src[u] = r[1];
+        len[u] = ok ? r[2] : 0u;
+    }
+}
+
+// ------------------------------------------------------------------- scans
+
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
 
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x)
 {
@@ -122,155 +242,109 @@ __device__ uint64_t wg_excl_scan64(uint64_t v, uint64_t *tmp, uint64_t &total)
     return before + x - v;
 }
 
-// ------------------------------------------------------------------ LDS state
-
-struct Lds {
-    union {
-        uint8_t stage[3][STAGE_PAD];   // raw cmd/len/lvl slices
-        uint64_t scan[K_MAX + 1];      // per run: (output offset << 32) | literal offset
-    } u;
-    uint32_t run[K_MAX + 1];
-    uint32_t mlen[K_MAX];
-    uint32_t lvl[K_MAX];
-    uint16_t rank[K_MAX];
-    uint32_t hist[LVL_LDS];
-    uint32_t hbase[LVL_LDS];
-    uint64_t tmp[NT / 64];
-    ChunkDesc d;
-    uint32_t bad;
-};
-
-// Decode exactly cnt LEB128 values from b[0, nb) into vals; false (uniform
-// over the workgroup) if the slice does not hold exactly cnt well-formed values.
-__device__ bool wg_varints(Lds &L, const uint8_t *b, uint32_t nb, uint32_t cnt, uint32_t *vals)
+// One wave decodes exactly cnt LEB128 values (at most 4 bytes each) from the
+// global bytes p[0, nb) into vals[0, cnt).  Lane i reads bytes 4i..4i+3 of each
+// 256-byte window; a value ends at a byte below 0x80, and its earlier bytes
+// are found by walking back through the 8-byte window made of the lane's
+// dword and its left neighbour's.  Returns true (uniformly) iff the slice
+// holds exactly cnt well-formed values.
+__device__ bool wave_varints(const uint8_t *p, uint32_t nb, uint32_t cnt, uint32_t *vals)
 {
-    const uint32_t t = threadIdx.x;
-    const uint32_t seg = (nb + NT - 1) / NT;
-    const uint32_t s0 = min(nb, t * seg), s1 = min(nb, s0 + seg);
-    uint32_t c = 0;
-    for (uint32_t i = s0; i < s1; i++) c += b[i] < 0x80;
-    uint64_t tot;
-    uint32_t idx = (uint32_t)wg_excl_scan64(c, L.tmp, tot);
-    if (tot != cnt || (nb && b[nb - 1] >= 0x80)) return false;
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t prev_last = 0;  // dword left of the window; zero bytes end any backward walk
+    uint32_t base = 0;
     bool ok = true;
-    for (uint32_t i = s0; i < s1; i++) {
-        if (b[i] >= 0x80) continue;
-        uint32_t k = i, ncont = 0;
-        while (k > 0 && b[k - 1] >= 0x80 && ncont < 4) { k--; ncont++; }
-        if (ncont > 3) { ok = false; break; }
-        uint32_t v = 0;
-        for (uint32_t q = 0; q <= ncont; q++) v |= (uint32_t)(b[k + q] & 0x7f) << (7 * q);
-        vals[idx++] = v;
-    }
-    if (!ok) L.bad = 1;
-    __syncthreads();
-    return L.bad == 0;
-}
-
-// stage one slice of the compressed stream into LDS (exact bytes, no over-read)
-__device__ __forceinline__ void stage_slice(uint8_t *dst, const uint8_t *src, uint32_t n)
-{
-    for (uint32_t i = threadIdx.x * 4; i < n; i += NT * 4) {
-        if (i + 4 <= n) {
-            *(uint32_t *)(dst + i) = ld32(src + i);
+    for (uint32_t w = 0; w < nb; w += 256) {
+        const uint32_t o = w + 4 * lane;
+        uint32_t v;
+        if (o + 4 <= nb) {
+            v = ld32(p + o);
         } else {
-            for (uint32_t k = i; k < n; k++) dst[k] = src[k];
+            v = 0x80808080u;  // bytes past the slice: continuation, never a value end
+            for (uint32_t k = 0; k < 4; k++)
+                if (o + k < nb) v = (v & ~(0xffu << (8 * k))) | ((uint32_t)p[o + k] << (8 * k));
         }
-    }
-}
-
-// Load and parse the chunk g into LDS.  Returns the number of cmd values
-// (> 0) or 0 when the chunk is skipped or corrupt (uniform).
-__device__ uint32_t parse_chunk(const Job &j, uint32_t g, Lds &L, bool want_lvl)
-{
-    const uint32_t t = threadIdx.x;
-    if (t < 12) ((uint32_t *)&L.d)[t] = ((const uint32_t *)(j.chunks + g))[t];
-    if (t == 0) L.bad = 0;
-    __syncthreads();
-    const ChunkDesc d = L.d;
-    if (d.nseq_last == SKIP) return 0;
-    const uint32_t ns = d.nseq_last & 0x7fffffffu;
-    const uint32_t ncmd = ns + (d.nseq_last >> 31);
-    stage_slice(L.u.stage[0], j.comp + d.cmd_at, d.cmd_n);
-    stage_slice(L.u.stage[1], j.comp + d.len_at, d.len_n);
-    if (want_lvl) stage_slice(L.u.stage[2], j.comp + d.lvl_at, d.lvl_n);
-    __syncthreads();
-    bool ok = wg_varints(L, L.u.stage[0], d.cmd_n, ncmd, L.run);
-    ok = ok && wg_varints(L, L.u.stage[1], d.len_n, ns, L.mlen);
-    if (want_lvl) ok = ok && wg_varints(L, L.u.stage[2], d.lvl_n, ns, L.lvl);
-    if (!ok) {
-        if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
-        return 0;
-    }
-    __syncthreads();  // the stage area is reused for the scan below
-    // per run: output bytes it spans together with its match, and literal bytes
-    const uint32_t per = (ncmd + NT - 1) / NT;
-    const uint32_t e0 = min(ncmd, t * per), e1 = min(ncmd, e0 + per);
-    uint64_t acc = 0;
-    bool bad = false;
-    for (uint32_t e = e0; e < e1; e++) {
-        uint32_t r = L.run[e];
-        uint32_t m = 0;
-        if (e < ns) {
-            m = L.mlen[e] + j.min_match;
-            L.mlen[e] = m;
-            if (m > d.out_len || (want_lvl && L.lvl[e] > j.max_level)) bad = true;
+        const uint32_t term = ~v & 0x80808080u;
+        const uint32_t c = __popc(term);
+        const uint32_t incl = wave_incl_scan32(c);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        uint32_t pv = __shfl_up(v, 1, 64);
+        if (lane == 0) pv = prev_last;
+        const uint64_t win = ((uint64_t)v << 32) | pv;
+        uint32_t idx = base + incl - c;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (!(term & (0x80u << (8 * k)))) continue;
+            uint32_t val = (v >> (8 * k)) & 0x7f;
+            int q = 3 + k, n = 0;
+            for (; n < 4; n++, q--) {
+                const uint32_t byte = (uint32_t)(win >> (8 * q)) & 0xff;
+                if (byte < 0x80) break;
+                val = (val << 7) | (byte & 0x7f);
+            }
+            if (n > 3) ok = false;
+            if (idx < cnt) vals[idx] = val;
+            idx++;
         }
-        if (r > d.out_len) bad = true;
-        acc += ((uint64_t)(r + m) << 32) | r;
+        base += tot;
+        prev_last = __shfl(v, 63, 64);
     }
-    uint64_t tot;
-    uint64_t ex = wg_excl_scan64(bad ? 0 : acc, L.tmp, tot);
-    for (uint32_t e = e0; e < e1; e++) {
-        L.u.scan[e] = ex;
-        uint32_t r = L.run[e];
-        uint32_t m = e < ns ? L.mlen[e] : 0;
-        ex += ((uint64_t)(r + m) << 32) | r;
-    }
-    if (bad) L.bad = 1;
-    __syncthreads();
-    if (L.bad || (uint32_t)(tot >> 32) != d.out_len || (uint32_t)tot != d.lit_n) {
-        if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
-        return 0;
-    }
-    return ncmd;
+    ok = ok && base == cnt && (nb == 0 || p[nb - 1] < 0x80);
+    return __ballot(!ok) == 0;
 }
 
-// --------------------------------------------------------------------- kernels
-
-__global__ void k_init(Job j)
-{
-    const uint32_t gid = blockIdx.x * NT + threadIdx.x, gsz = gridDim.x * NT;
-    if (gid == 0) *j.status = 0;
-    for (uint32_t i = gid; i <= j.max_level; i += gsz) {
-        j.hist[i] = 0;
-        j.cursor[i] = 0;
-    }
-    for (uint32_t i = gid; i < j.n_chunks; i += gsz) j.chunks[i].nseq_last = SKIP;
-}
+// --------------------------------------------------------------- k_setup
 
 __global__ void __launch_bounds__(NT) k_setup(Job j)
 {
     __shared__ uint32_t ok_blk;
+    __shared__ uint64_t tmp[NT / 64];
+    __shared__ uint32_t hist[LH];
+    __shared__ uint32_t vals[NT / 64][K_MAX];
+    const uint32_t t = threadIdx.x;
     const uint64_t B = (uint64_t)1 << j.block_log2;
     const uint32_t K = 1u << j.chunk_log2;
-    const uint64_t tbl_end = HDR + 16ull * (j.n_blocks + 1);
+    const uint64_t lvl_tab = HDR + 16ull * (j.n_blocks + 1);
+    const uint64_t prefix = lvl_tab + pad16(4ull * (j.max_level + 1));
+
+    if (blockIdx.x == 0) {
+        // level table -> first record of every level
+        if (t == 0) *j.status = 0;
+        uint64_t carry = 0;
+        for (uint32_t s = 0; s <= j.max_level; s += NT) {
+            const uint32_t i = s + t;
+            const uint32_t c = i <= j.max_level ? ld32(j.comp + lvl_tab + 4ull * i) : 0;
+            uint64_t tot;
+            const uint64_t ex = wg_excl_scan64(c, tmp, tot);
+            if (i <= j.max_level) {
+                const uint32_t rb = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
+                j.rec_base[i] = rb;
+                j.cursor[i] = rb;
+            }
+            carry += tot;
+        }
+        if (t == 0) {
+            j.rec_base[j.max_level + 1] = (uint32_t)min(carry, (uint64_t)j.n_seq);
+            if (carry != j.n_seq) fail(j, ACEAPEX_E_CORRUPT);  // every match counted exactly once
+        }
+    }
+
     for (uint32_t b = blockIdx.x; b < j.n_blocks; b += gridDim.x) {
         const uint8_t *tb = j.comp + HDR + 16ull * b;
         const uint64_t o0 = ld64(tb), o1 = ld64(tb + 16);
         const uint32_t sb0 = ld32(tb + 8), cb0 = ld32(tb + 12), sb1 = ld32(tb + 24), cb1 = ld32(tb + 28);
-        bool ok = (o0 & 15) == 0 && o0 >= tbl_end && o1 >= o0 + BLKHDR && o1 <= j.comp_bytes &&
+        bool ok = (o0 & 15) == 0 && o0 >= prefix && o1 >= o0 + BLKHDR && o1 <= j.comp_bytes &&
                   cb1 >= cb0 && cb1 <= j.n_chunks && sb1 >= sb0 && sb1 <= j.n_seq;
-        if (b == 0) ok = ok && cb0 == 0 && sb0 == 0;
+        if (b == 0) ok = ok && cb0 == 0 && sb0 == 0 && o0 == prefix;
         if (b + 1 == j.n_blocks) ok = ok && o1 == j.comp_bytes && cb1 == j.n_chunks && sb1 == j.n_seq;
         uint32_t ns = 0, nl = 0, nc = 0, cmdb = 0, lenb = 0, lvlb = 0;
         uint64_t off_at = 0, cmd_at = 0, len_at = 0, lvl_at = 0, lit_at = 0;
         if (ok) {
             const uint8_t *bh = j.comp + o0;
             ns = ld32(bh); nl = ld32(bh + 4); nc = ld32(bh + 8);
-            uint32_t bmax = ld32(bh + 12);
+            const uint32_t bmax = ld32(bh + 12);
             cmdb = ld32(bh + 16); lenb = ld32(bh + 20); lvlb = ld32(bh + 24);
-            uint32_t want_nc = ns ? (uint32_t)((ns + (uint64_t)K - 1) / K) : 1u;
+            const uint32_t want_nc = ns ? (uint32_t)((ns + (uint64_t)K - 1) / K) : 1u;
             ok = nc == cb1 - cb0 && ns == sb1 - sb0 && nc == want_nc && bmax <= j.max_level;
             off_at = o0 + BLKHDR + (uint64_t)CHUNK_ENT * nc;
             cmd_at = off_at + pad16(4ull * ns);
@@ -279,28 +353,26 @@ __global__ void __launch_bounds__(NT) k_setup(Job j)
             lit_at = lvl_at + pad16(lvlb);
             ok = ok && lit_at + pad16(nl) == o1;
         }
-        if (threadIdx.x == 0) ok_blk = ok;
+        if (t == 0) ok_blk = ok;
         __syncthreads();
-        if (!ok_blk) {
-            if (threadIdx.x == 0) fail(j, ACEAPEX_E_CORRUPT);
-            __syncthreads();
+        const bool blk_good = ok_blk;
+        __syncthreads();
+        if (!blk_good) {
+            if (t == 0) j.blk_ok[b] = 0;
             continue;
         }
         const uint32_t blen = (uint32_t)min(B, (uint64_t)j.n - b * B);
-        for (uint32_t c = threadIdx.x; c < nc; c += NT) {
+        bool all = true;
+        for (uint32_t c = t; c < nc; c += NT) {
             const uint8_t *e = j.comp + o0 + BLKHDR + (uint64_t)CHUNK_ENT * c;
-            uint32_t c0 = ld32(e), l0 = ld32(e + 4), v0 = ld32(e + 8), q0 = ld32(e + 12), d0 = ld32(e + 16);
+            const uint32_t c0 = ld32(e), l0 = ld32(e + 4), v0 = ld32(e + 8), q0 = ld32(e + 12), d0 = ld32(e + 16);
             uint32_t c1 = cmdb, l1 = lenb, v1 = lvlb, q1 = nl, d1 = blen;
             if (c + 1 < nc) { c1 = ld32(e + 32); l1 = ld32(e + 36); v1 = ld32(e + 40); q1 = ld32(e + 44); d1 = ld32(e + 48); }
             const uint32_t n_in = ns ? min(K, ns - c * K) : 0;
             const bool last = c + 1 == nc;
-            bool cok = c0 <= c1 && c1 <= cmdb && l0 <= l1 && l1 <= lenb && v0 <= v1 && v1 <= lvlb &&
-                       q0 <= q1 && q1 <= nl && d0 <= d1 && d1 <= blen &&
-                       c1 - c0 <= 4 * (n_in + 1) && l1 - l0 <= 4 * n_in && v1 - v0 <= 4 * n_in;
-            if (!cok) {
-                fail(j, ACEAPEX_E_CORRUPT);
-                continue;
-            }
+            const bool cok = c0 <= c1 && c1 <= cmdb && l0 <= l1 && l1 <= lenb && v0 <= v1 && v1 <= lvlb &&
+                             q0 <= q1 && q1 <= nl && d0 <= d1 && d1 <= blen &&
+                             c1 - c0 <= 4 * (n_in + 1) && l1 - l0 <= 4 * n_in && v1 - v0 <= 4 * n_in;
             ChunkDesc cd;
             cd.out_base = (uint32_t)(b * B) + d0;
             cd.out_len = d1 - d0;
@@ -310,145 +382,366 @@ __global__ void __launch_bounds__(NT) k_setup(Job j)
             cd.lit_at = (uint32_t)lit_at + q0; cd.lit_n = q1 - q0;
             cd.off_at = (uint32_t)(off_at + 4ull * c * K);
             cd.nseq_last = n_in | (last ? 0x80000000u : 0u);
+            if (!cok) {  // a descriptor that k_parse rejects
+                cd.out_len = 0xffffffffu;
+                all = false;
+            }
             j.chunks[cb0 + c] = cd;
         }
+        if (t == 0) ok_blk = 1;
+        __syncthreads();
+        if (!all) ok_blk = 0;
+        __syncthreads();
+        if (j.use_bcur && ok_blk) {
+            // matches of this block at every level, for the per-(level, block) record ranges
+            const uint32_t nh = min(j.max_level + 1, LH);
+            for (uint32_t i = t; i < nh; i += NT) hist[i] = 0;
+            for (uint32_t i = LH + t; i <= j.max_level; i += NT) j.bcount[(uint64_t)i * j.n_blocks + b] = 0;
+            __syncthreads();
+            bool vok = true;
+            if (lvlb == ns) {  // one byte per level
+                for (uint32_t i = t; i < ns; i += NT) {
+                    const uint32_t l = j.comp[lvl_at + i];
+                    if (l > j.max_level || (l & 0x80)) vok = false;
+                    else if (l < LH) atomicAdd(&hist[l], 1u);
+                    else atomicAdd(&j.bcount[(uint64_t)l * j.n_blocks + b], 1u);
+                }
+            } else {  // LEB128: one wave per chunk, through the chunk index
+                const uint32_t w = t >> 6;
+                for (uint32_t c = w; c < nc; c += NT / 64) {
+                    const uint8_t *e = j.comp + o0 + BLKHDR + (uint64_t)CHUNK_ENT * c;
+                    const uint32_t v0 = ld32(e + 8), v1 = c + 1 < nc ? ld32(e + 40) : lvlb;
+                    const uint32_t n_in = min(K, ns - c * K);
+                    if (!wave_varints(j.comp + lvl_at + v0, v1 - v0, n_in, vals[w])) {
+                        vok = false;
+                        continue;
+                    }
+                    for (uint32_t i = t & 63; i < n_in; i += 64) {
+                        const uint32_t l = vals[w][i];
+                        if (l > j.max_level) vok = false;
+                        else if (l < LH) atomicAdd(&hist[l], 1u);
+                        else atomicAdd(&j.bcount[(uint64_t)l * j.n_blocks + b], 1u);
+                    }
+                }
+            }
+            if (!vok) ok_blk = 0;
+            __syncthreads();
+            for (uint32_t i = t; i < nh; i += NT) j.bcount[(uint64_t)i * j.n_blocks + b] = hist[i];
+        }
+        if (t == 0) j.blk_ok[b] = (uint8_t)ok_blk;
         __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(NT) k_phase1(Job j)
-{
-    __shared__ Lds L;
-    const uint32_t t = threadIdx.x;
-    const uint32_t nh = min(j.max_level + 1, LVL_LDS);
-    for (uint32_t i = t; i < nh; i += NT) L.hist[i] = 0;
-    const uint32_t ncmd = parse_chunk(j, blockIdx.x, L, true);
-    if (!ncmd) return;
-    const ChunkDesc &d = L.d;
-    const uint32_t ns = d.nseq_last & 0x7fffffffu;
-    for (uint32_t e = t; e < ncmd; e += NT) {
-        const uint32_t r = L.run[e];
-        if (r) {
-            const uint64_t sc = L.u.scan[e];
-            copy_bytes(j.out + d.out_base + (uint32_t)(sc >> 32), j.comp + d.lit_at + (uint32_t)sc, r);
-        }
-    }
-    for (uint32_t e = t; e < ns; e += NT) {
-        const uint32_t l = L.lvl[e];
-        if (l == 0) continue;
-        if (l < LVL_LDS) atomicAdd(&L.hist[l], 1u);
-        else atomicAdd(&j.hist[l], 1u);
-    }
-    __syncthreads();
-    for (uint32_t i = t; i < nh; i += NT)
-        if (L.hist[i]) atomicAdd(&j.hist[i], L.hist[i]);
-}
-
-__global__ void __launch_bounds__(NT) k_lscan(Job j)
+// Per level l (one workgroup each): first record of every block's share of
+// the level, from the per-(level, block) counts.
+__global__ void __launch_bounds__(NT) k_bscan(Job j)
 {
     __shared__ uint64_t tmp[NT / 64];
-    uint64_t carry = 0;
-    for (uint32_t s = 0; s <= j.max_level; s += NT) {
-        const uint32_t i = s + threadIdx.x;
-        const uint32_t h = (i <= j.max_level && i > 0) ? j.hist[i] : 0;
-        uint64_t tot;
-        const uint64_t ex = wg_excl_scan64(h, tmp, tot);
-        if (i <= j.max_level) {
-            const uint64_t b = carry + ex;
-            j.base[i] = (uint32_t)min(b, (uint64_t)j.n_deep);
-            j.cursor[i] = (uint32_t)min(b, (uint64_t)j.n_deep);
+    for (uint32_t l = blockIdx.x; l <= j.max_level; l += gridDim.x) {
+        const uint64_t row = (uint64_t)l * j.n_blocks;
+        uint64_t carry = j.rec_base[l];
+        for (uint32_t s = 0; s < j.n_blocks; s += NT) {
+            const uint32_t b = s + threadIdx.x;
+            const uint32_t c = b < j.n_blocks ? j.bcount[row + b] : 0;
+            uint64_t tot;
+            const uint64_t ex = wg_excl_scan64(c, tmp, tot);
+            if (b < j.n_blocks) j.bcursor[row + b] = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
+            carry += tot;
         }
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        j.base[j.max_level + 1] = (uint32_t)min(carry, (uint64_t)j.n_deep);
-        if (carry != j.n_deep) fail(j, ACEAPEX_E_CORRUPT);
+        if (threadIdx.x == 0 && carry != j.rec_base[l + 1]) fail(j, ACEAPEX_E_CORRUPT);
+        __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(NT) k_phase2(Job j)
+// --------------------------------------------------------------- k_parse
+
+struct ParseLds {
+    uint32_t run[K_MAX + 1];     // LEB128 path: literal runs
+    uint32_t mlen[K_MAX];        // LEB128 path: match lengths - min_match
+    uint32_t lvl[K_MAX];         // LEB128 path: match levels
+    uint32_t lcount[LH];         // matches of the chunk per level (levels < LH)
+    uint32_t lbase[LH];          // record slot reserved for them
+    uint64_t tmp[NT / 64];
+    uint32_t bad;
+};
+
+// Descriptor checks that keep every access of the chunk inside the stream
+// and the output, whatever the workspace held before.
+__device__ __forceinline__ bool desc_in_bounds(const Job &j, const ChunkDesc &d, uint32_t K)
 {
-    __shared__ Lds L;
-    const uint32_t t = threadIdx.x;
-    const uint32_t nh = min(j.max_level + 1, LVL_LDS);
-    for (uint32_t i = t; i < nh; i += NT) L.hist[i] = 0;
-    const uint32_t ncmd = parse_chunk(j, blockIdx.x, L, true);
-    if (!ncmd) return;
-    const ChunkDesc &d = L.d;
     const uint32_t ns = d.nseq_last & 0x7fffffffu;
+    return ns <= K && (uint64_t)d.out_base + d.out_len <= j.n &&
+           (uint64_t)d.cmd_at + d.cmd_n <= j.comp_bytes && d.cmd_n <= 4 * (ns + 1) &&
+           (uint64_t)d.len_at + d.len_n <= j.comp_bytes && d.len_n <= 4 * ns &&
+           (uint64_t)d.lvl_at + d.lvl_n <= j.comp_bytes && d.lvl_n <= 4 * ns &&
+           (uint64_t)d.lit_at + d.lit_n <= j.comp_bytes && (uint64_t)d.off_at + 4ull * ns <= j.comp_bytes;
+}
+
+// The 4 bytes of a one-byte-per-value slice that belong to values [e, e+4),
+// zero past the slice's count.
+__device__ __forceinline__ uint32_t bytes4(const uint8_t *p, uint32_t e, uint32_t cnt)
+{
+    if (e + 4 <= cnt) return ld32(p + e);
+    uint32_t v = 0;
+    for (uint32_t k = 0; k < 4; k++)
+        if (e + k < cnt) v |= (uint32_t)p[e + k] << (8 * k);
+    return v;
+}
+
+__global__ void __launch_bounds__(NT) k_parse(Job j)
+{
+    __shared__ ParseLds L;
+    const uint32_t t = threadIdx.x, wave = t >> 6;
+    const uint32_t K = 1u << j.chunk_log2;
+    const uint32_t nl = min(j.max_level + 1, LH);
+
+    if (blockIdx.x == 0) {  // any block that failed its checks fails the decode
+        bool bad = false;
+        for (uint32_t b = t; b < j.n_blocks; b += NT) bad |= j.blk_ok[b] == 0;
+        if (bad) fail(j, ACEAPEX_E_CORRUPT);
+    }
+    const ChunkDesc d = j.chunks[xcd_slot(blockIdx.x, gridDim.x)];
+    if (t == 0) L.bad = 0;
+    for (uint32_t i = t; i < nl; i += NT) L.lcount[i] = 0;
+    __syncthreads();
+    const uint32_t blk = d.out_base >> j.block_log2;
+    if (!desc_in_bounds(j, d, K) || blk >= j.n_blocks) {
+        if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
+        return;
+    }
+    const uint32_t ns = d.nseq_last & 0x7fffffffu;
+    const uint32_t ncmd = ns + (d.nseq_last >> 31);
+    const bool one_byte = d.cmd_n == ncmd && d.len_n == ns && d.lvl_n == ns;
+    const uint32_t e0 = t * PER;
+
+    // this thread's sequences e0 .. e0+3: run, match length and level
+    uint32_t r[PER], m[PER], l[PER], src[PER];
     bool bad = false;
-    for (uint32_t e = t; e < ns; e += NT) {
-        const uint32_t dst = d.out_base + (uint32_t)(L.u.scan[e] >> 32) + L.run[e];
-        const uint32_t src = ld32(j.comp + d.off_at + 4 * e);
-        const uint32_t m = L.mlen[e];
-        const uint32_t l = L.lvl[e];
-        if ((uint64_t)src + m > dst) {  // a source must end before its destination
+    {
+        const u128u o4 = e0 + PER <= ns ? *(const u128u *)(j.comp + d.off_at + 4 * e0) : u128u{0, 0, 0, 0};
+        src[0] = o4.a; src[1] = o4.b; src[2] = o4.c; src[3] = o4.d;
+        if (e0 + PER > ns)
+            for (uint32_t u = 0; u < PER; u++) src[u] = e0 + u < ns ? ld32(j.comp + d.off_at + 4 * (e0 + u)) : 0;
+    }
+    if (one_byte) {
+        const uint32_t cw = bytes4(j.comp + d.cmd_at, e0, ncmd);
+        const uint32_t lw = bytes4(j.comp + d.len_at, e0, ns);
+        const uint32_t vw = bytes4(j.comp + d.lvl_at, e0, ns);
+        if ((cw | lw | vw) & 0x80808080u) bad = true;  // a continuation byte where every value is one byte
+#pragma unroll
+        for (uint32_t u = 0; u < PER; u++) {
+            r[u] = (cw >> (8 * u)) & 0xff;
+            m[u] = e0 + u < ns ? ((lw >> (8 * u)) & 0xff) + j.min_match : 0;
+            l[u] = (vw >> (8 * u)) & 0xff;
+        }
+    } else {
+        bool ok = true;
+        if (wave == 0) ok = wave_varints(j.comp + d.cmd_at, d.cmd_n, ncmd, L.run);
+        else if (wave == 1) ok = wave_varints(j.comp + d.len_at, d.len_n, ns, L.mlen);
+        else if (wave == 2) ok = wave_varints(j.comp + d.lvl_at, d.lvl_n, ns, L.lvl);
+        if (!ok && (t & 63) == 0) L.bad = 1;
+        __syncthreads();
+        if (L.bad) {
+            if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
+            return;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < PER; u++) {
+            const uint32_t e = e0 + u;
+            r[u] = e < ncmd ? L.run[e] : 0;
+            m[u] = e < ns ? L.mlen[e] + j.min_match : 0;
+            l[u] = e < ns ? L.lvl[e] : 0;
+        }
+    }
+
+    // output and literal offsets: workgroup scan over (run + match, run)
+    uint64_t acc = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < PER; u++) {
+        if (r[u] > d.out_len || m[u] > d.out_len || (e0 + u < ns && l[u] > j.max_level)) bad = true;
+        acc += ((uint64_t)(r[u] + m[u]) << 32) | r[u];
+    }
+    uint64_t tot;
+    const uint64_t ex = wg_excl_scan64(bad ? 0 : acc, L.tmp, tot);
+    if (bad) L.bad = 1;
+    __syncthreads();
+    if (L.bad || (uint32_t)(tot >> 32) != d.out_len || (uint32_t)tot != d.lit_n) {
+        if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
+        return;
+    }
+
+    // literal runs to their output positions; destinations of the matches
+    uint32_t pos = d.out_base + (uint32_t)(ex >> 32), lq = (uint32_t)ex;
+    uint32_t dst[PER], rank[PER];
+#pragma unroll
+    for (uint32_t u = 0; u < PER; u++) {
+        if (r[u]) copy_bytes(j.out + pos, j.comp + d.lit_at + lq, r[u]);
+        pos += r[u];
+        lq += r[u];
+        dst[u] = pos;
+        pos += m[u];
+    }
+
+    // every match -> record in the bucket of its level
+#pragma unroll
+    for (uint32_t u = 0; u < PER; u++) {
+        rank[u] = 0xffffffffu;
+        if (e0 + u >= ns) continue;
+        if ((uint64_t)src[u] + m[u] > dst[u]) {  // a source must end before its destination
             bad = true;
-            L.lvl[e] = SKIP;
             continue;
         }
-        if (l == 0) {
-            copy_bytes(j.out + dst, j.out + src, m);
-        } else if (l < LVL_LDS) {
-            L.rank[e] = (uint16_t)atomicAdd(&L.hist[l], 1u);
+        if (l[u] < LH) {
+            rank[u] = atomicAdd(&L.lcount[l[u]], 1u);
+        } else {
+            const uint32_t slot = atomicAdd(j.use_bcur ? &j.bcursor[(uint64_t)l[u] * j.n_blocks + blk]
+                                                       : &j.cursor[l[u]], 1u);
+            if (slot < j.rec_base[l[u] + 1]) {
+                uint32_t *rr = j.recs + 3ull * slot;
+                rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u];
+            } else {
+                bad = true;
+            }
         }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < nl; i += NT)
+        if (L.lcount[i])
+            L.lbase[i] = atomicAdd(j.use_bcur ? &j.bcursor[(uint64_t)i * j.n_blocks + blk] : &j.cursor[i],
+                                   L.lcount[i]);
+    __syncthreads();
+#pragma unroll
+    for (uint32_t u = 0; u < PER; u++) {
+        if (rank[u] == 0xffffffffu) continue;
+        const uint32_t slot = L.lbase[l[u]] + rank[u];
+        if (slot >= j.rec_base[l[u] + 1]) {  // more matches than the level table announced
+            bad = true;
+            continue;
+        }
+        uint32_t *rr = j.recs + 3ull * slot;
+        rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u];
     }
     if (bad) fail(j, ACEAPEX_E_CORRUPT);
-    __syncthreads();
-    for (uint32_t i = t; i < nh; i += NT)
-        if (L.hist[i]) L.hbase[i] = atomicAdd(&j.cursor[i], L.hist[i]);
-    __syncthreads();
-    for (uint32_t e = t; e < ns; e += NT) {
-        const uint32_t l = L.lvl[e];
-        if (l == 0 || l == SKIP) continue;
-        const uint32_t slot = l < LVL_LDS ? L.hbase[l] + L.rank[e] : atomicAdd(&j.cursor[l], 1u);
-        if (slot >= j.base[l + 1]) {  // more deep matches than the histogram announced
-            fail(j, ACEAPEX_E_CORRUPT);
-            continue;
-        }
-        const uint32_t dst = d.out_base + (uint32_t)(L.u.scan[e] >> 32) + L.run[e];
-        uint32_t *r = j.recs + 3ull * slot;
-        r[0] = dst;
-        r[1] = ld32(j.comp + d.off_at + 4 * e);
-        r[2] = L.mlen[e];
-    }
 }
 
+// --------------------------------------------------------------- k_level
+
+// The level's records are split into one contiguous part per XCD; the
+// workgroups of an XCD sweep its part together, tile after tile, so that the
+// destinations and in-block sources they touch at one time share its L2.
 __global__ void __launch_bounds__(NT) k_level(Job j, uint32_t k)
 {
-    const uint32_t b0 = j.base[k];
-    const uint32_t b1 = min(j.cursor[k], j.base[k + 1]);
-    for (uint32_t i = b0 + blockIdx.x * NT + threadIdx.x; i < b1; i += gridDim.x * NT) {
-        const uint32_t *r = j.recs + 3ull * i;
-        const uint32_t dst = r[0], src = r[1], m = r[2];
-        if ((uint64_t)dst + m > j.n || (uint64_t)src + m > dst) {
-            fail(j, ACEAPEX_E_CORRUPT);
-            continue;
-        }
-        copy_bytes(j.out + dst, j.out + src, m);
+    const uint32_t R0 = j.rec_base[k];
+    const uint32_t R1 = j.use_bcur ? j.rec_base[k + 1] : min(j.cursor[k], j.rec_base[k + 1]);
+    const uint32_t G = gridDim.x, P = G < 8 ? G : 8;
+    const uint32_t x = blockIdx.x % P, w = blockIdx.x / P, W = (G - x + P - 1) / P;
+    const uint64_t S = R1 > R0 ? R1 - R0 : 0;
+    const uint32_t p0 = R0 + (uint32_t)(S * x / P), p1 = R0 + (uint32_t)(S * (x + 1) / P);
+    bool bad = false;
+    for (uint32_t r0 = p0 + w * (NT * ROUND) + threadIdx.x;; r0 += W * (NT * ROUND)) {
+        if (__ballot(r0 < p1) == 0) break;
+        uint32_t dst[ROUND], src[ROUND], len[ROUND];
+        load_records(j, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, dst, src, len);
+        run_records(j, dst, src, len, bad);
     }
+    if (bad) fail(j, ACEAPEX_E_CORRUPT);
+}
+
+// The tail of deep levels [k0, max_level] in one workgroup of NT_TAIL threads.
+__global__ void __launch_bounds__(NT_TAIL) k_tail(Job j, uint32_t k0)
+{
+    bool bad = false;
+    for (uint32_t k = k0; k <= j.max_level; k++) {
+        const uint32_t r_end = j.use_bcur ? j.rec_base[k + 1] : min(j.cursor[k], j.rec_base[k + 1]);
+        for (uint32_t r0 = j.rec_base[k] + threadIdx.x;; r0 += ROUND * NT_TAIL) {
+            if (__ballot(r0 < r_end) == 0) break;
+            uint32_t dst[ROUND], src[ROUND], len[ROUND];
+            load_records(j, min(r0, r_end - 1), NT_TAIL, r0 < r_end ? r_end : 0, dst, src, len);
+            run_records(j, dst, src, len, bad);
+        }
+        __syncthreads();
+    }
+    if (bad) fail(j, ACEAPEX_E_CORRUPT);
 }
 
 // ----------------------------------------------------------------- host side
 
 thread_local int g_last_hip = 0;
 
+// Kernel timing for measurement (off by default): while enabled, every kernel
+// group of a decode is bracketed by two HIP events on the decode's stream.
+enum Phase { PH_SETUP, PH_PARSE, PH_LEVELS, PH_COUNT };
+
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> marks;  // (phase, index of its start event)
+};
+thread_local Timing g_timing;
+
+hipEvent_t timing_event()
+{
+    Timing &t = g_timing;
+    if (t.used == t.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        t.pool.push_back(e);
+    }
+    return t.pool[t.used++];
+}
+
+struct PhaseScope {
+    int ph;
+    hipStream_t st;
+    size_t i0 = 0;
+    bool on;
+    PhaseScope(int p, hipStream_t s) : ph(p), st(s), on(g_timing.on)
+    {
+        if (!on) return;
+        i0 = g_timing.used;
+        hipEvent_t e = timing_event();
+        if (!e) { on = false; return; }
+        hipEventRecord(e, st);
+    }
+    ~PhaseScope()
+    {
+        if (!on) return;
+        hipEvent_t e = timing_event();
+        if (!e) return;
+        hipEventRecord(e, st);
+        g_timing.marks.push_back({ph, i0});
+    }
+};
+
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+constexpr uint64_t BCUR_MAX = 1ull << 22;  // (level, block) cursors used up to this many pairs
+
+bool use_block_cursors(const aceapex_info &in)
+{
+    return (uint64_t)in.n_blocks * ((uint64_t)in.max_level + 1) <= BCUR_MAX;
+}
+
 struct WsLayout {
-    size_t status, chunks, hist, base, cursor, recs, total;
+    size_t status, chunks, blk_ok, rec_base, cursor, bcount, bcursor, recs, total;
 };
 
 WsLayout ws_layout(const aceapex_info &in)
 {
     WsLayout w;
     size_t o = 0;
+    const size_t nl = (size_t)in.max_level + 1;
     w.status = o; o += 256;
     w.chunks = o; o = align256(o + sizeof(ChunkDesc) * (size_t)in.n_chunks);
-    w.hist = o; o = align256(o + 4ull * ((size_t)in.max_level + 1));
-    w.base = o; o = align256(o + 4ull * ((size_t)in.max_level + 2));
-    w.cursor = o; o = align256(o + 4ull * ((size_t)in.max_level + 1));
-    w.recs = o; o = align256(o + 12ull * (size_t)in.n_deep);
+    w.blk_ok = o; o = align256(o + (size_t)in.n_blocks);
+    w.rec_base = o; o = align256(o + 4 * (nl + 1));
+    w.cursor = o; o = align256(o + 4 * nl);
+    const size_t pairs = use_block_cursors(in) ? nl * (size_t)in.n_blocks : 0;
+    w.bcount = o; o = align256(o + 4 * pairs);
+    w.bcursor = o; o = align256(o + 4 * pairs);
+    w.recs = o; o = align256(o + 12ull * (size_t)in.n_seq);
     w.total = o;
     return w;
 }
@@ -457,12 +750,17 @@ inline uint16_t rd16h(const uint8_t *p) { uint16_t v; memcpy(&v, p, 2); return v
 inline uint32_t rd32h(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
 inline uint64_t rd64h(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
 
+uint64_t prefix_bytes(const aceapex_info &in)
+{
+    return HDR + 16ull * (in.n_blocks + 1ull) + ((4ull * (in.max_level + 1ull) + 15) & ~15ull);
+}
+
 bool info_consistent(const aceapex_info &in)
 {
     if (in.block_log2 < 3 || in.block_log2 > 30 || in.min_match < 1 || in.chunk_log2 > 20) return false;
     const uint64_t B = 1ull << in.block_log2;
     if ((in.decoded_bytes + B - 1) / B != in.n_blocks) return false;
-    if (in.comp_bytes < HDR + 16ull * (in.n_blocks + 1ull)) return false;
+    if (in.max_level >= (1u << 28) || in.comp_bytes < prefix_bytes(in)) return false;
     if (in.n_deep > in.n_seq) return false;
     if (in.n_blocks == 0 && (in.n_seq || in.n_chunks)) return false;
     if (in.n_blocks && in.n_chunks < in.n_blocks) return false;
@@ -473,7 +771,7 @@ int gpu_supported(const aceapex_info &in)
 {
     if (in.decoded_bytes >= (1ull << 32) || in.comp_bytes >= (1ull << 32)) return ACEAPEX_E_UNSUPPORTED;
     if (in.block_log2 > BLOCK_LOG2_MAX || in.chunk_log2 > K_LOG2_MAX) return ACEAPEX_E_UNSUPPORTED;
-    if (in.max_level >= (1u << 28)) return ACEAPEX_E_UNSUPPORTED;
+    if ((uint64_t)in.n_seq * 3 >= (1ull << 32)) return ACEAPEX_E_UNSUPPORTED;
     return ACEAPEX_OK;
 }
 
@@ -483,8 +781,13 @@ int hip_fail(hipError_t e)
     return ACEAPEX_E_HIP;
 }
 
-int launch_one(const aceapex_stream &s, void *d_out, uint64_t cap, uint8_t *ws, int32_t *d_status,
-               hipStream_t st)
+uint32_t level_wgs(uint64_t records)
+{
+    const uint64_t per_wg = (uint64_t)NT * ROUND;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(LEVEL_WG_MAX, (records + per_wg - 1) / per_wg));
+}
+
+int launch_one(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st)
 {
     const aceapex_info &in = s.info;
     const WsLayout w = ws_layout(in);
@@ -500,23 +803,43 @@ int launch_one(const aceapex_stream &s, void *d_out, uint64_t cap, uint8_t *ws, 
     j.max_level = in.max_level;
     j.n_chunks = in.n_chunks;
     j.n_seq = in.n_seq;
-    j.n_deep = in.n_deep;
     j.chunks = (ChunkDesc *)(ws + w.chunks);
-    j.hist = (uint32_t *)(ws + w.hist);
-    j.base = (uint32_t *)(ws + w.base);
+    j.blk_ok = ws + w.blk_ok;
+    j.rec_base = (uint32_t *)(ws + w.rec_base);
     j.cursor = (uint32_t *)(ws + w.cursor);
+    j.bcount = (uint32_t *)(ws + w.bcount);
+    j.bcursor = (uint32_t *)(ws + w.bcursor);
+    j.use_bcur = use_block_cursors(in) ? 1u : 0u;
     j.recs = (uint32_t *)(ws + w.recs);
     j.status = d_status ? d_status : (int32_t *)(ws + w.status);
-    (void)cap;
-    const uint32_t init_grid = (uint32_t)std::min<uint64_t>(1024, (std::max<uint64_t>(in.n_chunks, in.max_level + 1ull) + NT - 1) / NT + 1);
-    hipLaunchKernelGGL(k_init, dim3(init_grid), dim3(NT), 0, st, j);
+    {
+        PhaseScope ps(PH_SETUP, st);
+        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(in.n_blocks, 65535));
+        hipLaunchKernelGGL(k_setup, dim3(g), dim3(NT), 0, st, j);
+    }
     if (in.n_blocks) {
-        hipLaunchKernelGGL(k_setup, dim3(std::min<uint32_t>(in.n_blocks, 65535)), dim3(NT), 0, st, j);
-        hipLaunchKernelGGL(k_phase1, dim3(in.n_chunks), dim3(NT), 0, st, j);
-        hipLaunchKernelGGL(k_lscan, dim3(1), dim3(NT), 0, st, j);
-        hipLaunchKernelGGL(k_phase2, dim3(in.n_chunks), dim3(NT), 0, st, j);
-        for (uint32_t k = 1; k <= in.max_level; k++)
-            hipLaunchKernelGGL(k_level, dim3(LEVEL_GRID), dim3(NT), 0, st, j, k);
+        {
+            PhaseScope ps(PH_PARSE, st);
+            if (j.use_bcur)
+                hipLaunchKernelGGL(k_bscan, dim3(std::min<uint32_t>(in.max_level + 1, 65535)), dim3(NT), 0, st, j);
+            hipLaunchKernelGGL(k_parse, dim3(in.n_chunks), dim3(NT), 0, st, j);
+        }
+        if (in.n_seq) {
+            PhaseScope ps(PH_LEVELS, st);
+            // with the level table on the host: one launch per level sized to it, and
+            // the deep levels that hold few matches together in the tail workgroup
+            uint32_t tail = in.max_level + 1;
+            if (s.h_levels) {
+                while (tail > 1 && s.h_levels[tail - 1] <= TAIL_LEVEL_MAX) tail--;
+                if (in.max_level + 1 - tail < 2) tail = in.max_level + 1;
+            }
+            for (uint32_t k = 0; k < tail; k++) {
+                const uint64_t cnt = s.h_levels ? s.h_levels[k] : in.n_seq;
+                if (s.h_levels && !cnt) continue;
+                hipLaunchKernelGGL(k_level, dim3(level_wgs(cnt)), dim3(NT), 0, st, j, k);
+            }
+            if (tail <= in.max_level) hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT_TAIL), 0, st, j, tail);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e);
@@ -564,6 +887,21 @@ int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info)
     return ACEAPEX_OK;
 }
 
+int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *counts, uint32_t n)
+{
+    aceapex_info in;
+    int rc = aceapex_probe(h_stream_prefix, h_len, &in);
+    if (rc) return rc;
+    const uint64_t at = HDR + 16ull * (in.n_blocks + 1ull), cnt = (uint64_t)in.max_level + 1;
+    if (!counts || n < cnt || h_len < at + 4 * cnt) return ACEAPEX_E_INVAL;
+    uint64_t sum = 0;
+    for (uint64_t i = 0; i < cnt; i++) {
+        counts[i] = rd32h((const uint8_t *)h_stream_prefix + at + 4 * i);
+        sum += counts[i];
+    }
+    return sum == in.n_seq ? ACEAPEX_OK : ACEAPEX_E_FORMAT;
+}
+
 size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n)
 {
     if (!h_descs) return 0;
@@ -582,7 +920,7 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
     if (rc) return rc;
     const size_t need = ws_layout(stream->info).total;
     if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need) return ACEAPEX_E_WORKSPACE;
-    return launch_one(*stream, d_out, out_capacity, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream);
+    return launch_one(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream);
 }
 
 int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace, size_t ws_bytes,
@@ -598,8 +936,8 @@ int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspa
     if (n && (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need)) return ACEAPEX_E_WORKSPACE;
     size_t off = 0;
     for (uint32_t i = 0; i < n; i++) {
-        int rc = launch_one(h_descs[i].s, h_descs[i].d_out, h_descs[i].out_capacity,
-                            (uint8_t *)d_workspace + off, h_descs[i].d_status, (hipStream_t)hip_stream);
+        int rc = launch_one(h_descs[i].s, h_descs[i].d_out, (uint8_t *)d_workspace + off, h_descs[i].d_status,
+                            (hipStream_t)hip_stream);
         if (rc) return rc;
         off += ws_layout(h_descs[i].s.info).total;
     }
@@ -618,10 +956,40 @@ const char *aceapex_strerror(int code)
     case ACEAPEX_E_UNSUPPORTED: return "stream outside the limits of this decoder";
     case ACEAPEX_E_TIMEOUT: return "device wait timed out";
     case ACEAPEX_E_HIP: return "HIP runtime error";
+    case ACEAPEX_E_NOMEM: return "host allocation failed";
     default: return "unknown error";
     }
 }
 
 int aceapex_last_hip_error(void) { return g_last_hip; }
+
+int aceapex_timing(int enable)
+{
+    Timing &t = g_timing;
+    t.on = enable != 0;
+    t.used = 0;
+    t.marks.clear();
+    return ACEAPEX_OK;
+}
+
+int aceapex_timing_read(float *ms, uint32_t *count, uint32_t n)
+{
+    if (!ms || !count) return ACEAPEX_E_INVAL;
+    Timing &t = g_timing;
+    for (uint32_t i = 0; i < n; i++) { ms[i] = 0.f; count[i] = 0; }
+    if (t.used) {
+        hipError_t e = hipEventSynchronize(t.pool[t.used - 1]);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    for (const auto &m : t.marks) {
+        float v = 0.f;
+        hipError_t e = hipEventElapsedTime(&v, t.pool[m.second], t.pool[m.second + 1]);
+        if (e != hipSuccess) return hip_fail(e);
+        if ((uint32_t)m.first < n) { ms[m.first] += v; count[m.first]++; }
+    }
+    t.used = 0;
+    t.marks.clear();
+    return ACEAPEX_OK;
+}
 
 }  // extern "C"

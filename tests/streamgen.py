@@ -84,7 +84,7 @@ def random_tokens(rng: np.random.Generator, n: int, block_log2: int, min_match: 
 
 def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
           chunk_log2: int = 10, levels=None, flags: int = 8, max_depth: int = 0,
-          max_level=None, n_deep=None) -> np.ndarray:
+          max_level=None, n_deep=None, level_counts=None) -> np.ndarray:
     """Serialize token lists into the stream layout (levels from the definition by default)."""
     decoded, exact = execute(blocks, lits, n, block_log2)
     if levels is None:
@@ -132,7 +132,15 @@ def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
         tot_seq += len(seqs)
         tot_chunks += len(chunks)
     table_len = 16 * (nb + 1)
-    pos = 64 + table_len
+    mlev = gmax if max_level is None else max_level
+    hist = [0] * (mlev + 1)
+    for lv in levels:
+        if lv <= mlev:
+            hist[lv] += 1
+    if level_counts is not None:
+        hist = list(level_counts)
+    hist_bytes = _pad(b"".join(int(v).to_bytes(4, "little") for v in hist))
+    pos = 64 + table_len + len(hist_bytes)
     offsets = []
     for pl in payloads:
         offsets.append(pos)
@@ -155,6 +163,6 @@ def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
     hdr[40:44] = tot_seq.to_bytes(4, "little")
     hdr[44:48] = (deep if n_deep is None else n_deep).to_bytes(4, "little")
     hdr[48:52] = tot_chunks.to_bytes(4, "little")
-    s = bytes(hdr) + table + b"".join(payloads)
+    s = bytes(hdr) + table + hist_bytes + b"".join(payloads)
     assert len(s) == comp
     return np.frombuffer(s, dtype=np.uint8).copy(), decoded

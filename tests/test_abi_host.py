@@ -53,16 +53,13 @@ def test_probe_rejects_bad_headers():
         assert e.value.code == _abi.E_FORMAT, i
 
 
-def test_workspace_bytes_scales_with_deep_matches():
+def test_workspace_bytes_covers_every_match_record():
     x = synth.markov(1 << 20, 4)
     a = oracle.encode(x, block_log2=18)
-    b = oracle.encode(x, block_log2=18, max_depth=1)
-    ia, ib = _abi.probe(a), _abi.probe(b)
-    wa = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia), 0, ia.decoded_bytes, 0)])
-    wb = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ib), 0, ib.decoded_bytes, 0)])
-    assert ib.n_deep == 0 and ia.n_deep > 0
-    assert wa - wb >= 12 * ia.n_deep
-    two = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia), 0, 0, 0)] * 2)
+    ia = _abi.probe(a)
+    wa = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia, None), 0, ia.decoded_bytes, 0)])
+    assert wa >= 12 * ia.n_seq + 48 * ia.n_chunks
+    two = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia, None), 0, 0, 0)] * 2)
     assert two == 2 * wa
 
 
@@ -70,10 +67,10 @@ def test_host_argument_errors_need_no_gpu():
     s = oracle.encode(synth.markov(5000, 1), block_log2=12)
     info = _abi.probe(s)
     lib = _abi.load()
-    st = _abi.Stream(0, info)
+    st = _abi.Stream(0, info, None)
     # null compressed pointer
     assert lib.aceapex_decode(ctypes.byref(st), 4096, info.decoded_bytes, 4096, 1 << 20, None, None) == _abi.E_INVAL
-    st = _abi.Stream(16, info)
+    st = _abi.Stream(16, info, None)
     # output too small
     assert lib.aceapex_decode(ctypes.byref(st), 4096, info.decoded_bytes - 1, 4096, 1 << 20, None, None) == _abi.E_CAPACITY
     # misaligned output
@@ -84,7 +81,24 @@ def test_host_argument_errors_need_no_gpu():
     # outside the GPU limits: 2^21-byte blocks
     big = oracle.encode(synth.markov(5000, 1), block_log2=21)
     ib = _abi.probe(big)
-    sb = _abi.Stream(16, ib)
+    sb = _abi.Stream(16, ib, None)
     assert lib.aceapex_decode(ctypes.byref(sb), 4096, ib.decoded_bytes, 4096, 1 << 20, None, None) == _abi.E_UNSUPPORTED
     assert _abi.strerror(_abi.E_CORRUPT) == "corrupt stream"
     assert lib.aceapex_decode_many(None, 0, None, 0, None) == _abi.OK
+
+
+def test_level_table_matches_tokens():
+    x = synth.fastq(2 << 20, 8)
+    s = oracle.encode(x, block_log2=17, flatten=1)
+    info = _abi.probe(s)
+    counts = list(_abi.level_table(s, info))
+    import numpy as np
+
+    assert counts == list(np.bincount(oracle.tokens(s)["lvl"], minlength=info.max_level + 1))
+    with pytest.raises(_abi.AceapexError):
+        _abi.level_table(s[:70], info)
+    bad = s.copy()
+    at = 64 + 16 * (info.n_blocks + 1)
+    bad[at] ^= 1
+    with pytest.raises(_abi.AceapexError):
+        _abi.level_table(bad, info)

@@ -157,3 +157,36 @@ def test_stale_output_and_workspace_do_not_matter():
         ax.decode(ds, out=out, workspace=ws)
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), x)
+
+
+@pytest.mark.parametrize("with_table", [True, False], ids=["level_table", "no_table"])
+def test_level_schedule_with_and_without_host_table(with_table):
+    """The wavefront is launched per level from the host copy of the level
+    table (deep sparse levels grouped in one workgroup) or, without it, with
+    full-size launches for every level; both give the same bytes."""
+    import torch
+
+    import paper_2606_04268_amd as ax
+
+    x = synth.fastq(3 << 20, 21)
+    s = oracle.encode(x, block_log2=16, flatten=1)
+    ds = ax.to_device(s)
+    if not with_table:
+        ds.levels = None
+    say(f"[gpu] schedule with_table={with_table} max_level={ds.info.max_level}")
+    out, st = ax.decode(ds)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert np.array_equal(out[: ds.n].cpu().numpy(), x)
+
+
+def test_many_blocks_many_levels():
+    """2100 blocks of 8 bytes, each one match copying the previous block:
+    levels 0..2099, more (level, block) pairs than the per-block record
+    cursors cover, so records are reserved per level instead."""
+    m = 2100
+    blocks = [([], 8)] + [([(0, 8, 8 * (b - 1))], 0) for b in range(1, m + 1)]
+    n = 8 * (m + 1)
+    s, want = streamgen.build(blocks, bytes(range(8)), n, block_log2=3, chunk_log2=2)
+    assert oracle.header_fields(s)["max_level"] == m - 1
+    parity(np.frombuffer(want, np.uint8), s, "chain-of-blocks")

@@ -212,7 +212,7 @@ def test_edge_cases():
             assert oracle.refdec(s) == x
     s = oracle.encode(b"")
     h = oracle.header_fields(s)
-    assert h["n_blocks"] == 0 and h["comp_bytes"] == 80 and h["n_seq"] == 0
+    assert h["n_blocks"] == 0 and h["comp_bytes"] == 96 and h["n_seq"] == 0
 
 
 def test_sequences_multiple_of_chunk():
