@@ -11,6 +11,15 @@ resident original and its XXH3-64 with the header's.
 Default workload: 256 MiB FASTQ-like stream (seeded synthetic), 1 MiB blocks,
 minimum match 4, chain flattening on.  Prints ONE JSON line on stdout;
 progress goes to stderr.
+
+Other modes (one JSON line each):
+  --mode batched  4096 streams of the text / FASTQ / random mix, sizes
+                  log-uniform 4 KiB..64 MiB, decoded by one aceapex_decode_many
+                  call, against a loop of one aceapex_decode call per stream.
+  --mode served   Poisson arrivals of decode requests (sizes log-uniform
+                  64 KiB..256 MiB, same mix) under a 200 GB device-memory
+                  budget, continuous batching against one-request-at-a-time,
+                  swept over offered loads; p50 / p99 latency and decoded GB/s.
 """
 from __future__ import annotations
 
@@ -96,6 +105,212 @@ def cpu_baseline(stream, x, budget_s: float = 12.0) -> dict:
             "host_threads_visible": len(os.sched_getaffinity(0))}
 
 
+def base_line(value, steps, warmup, ms):
+    return {"metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic"}
+
+
+MIX_ENC = {"markov": dict(), "fastq": dict(flatten=1), "random": dict()}
+
+
+def build_pool(recipe):
+    """Generate and encode the (kind, size, seed) recipe on the host cores;
+    returns [(original, stream)] in recipe order."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import synth
+    import paper_2606_04268_amd as ax
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def one(r):
+        kind, size, seed = r
+        x = synth.make(kind, size, seed)
+        return x, ax.encode(x, threads=4, **MIX_ENC[kind])
+
+    t0 = time.perf_counter()
+    order = sorted(range(len(recipe)), key=lambda i: -recipe[i][1])
+    res = [None] * len(recipe)
+    with ThreadPoolExecutor(workers) as ex:
+        for i, r in zip(order, ex.map(one, [recipe[i] for i in order])):
+            res[i] = r
+    tot = sum(r[1] for r in recipe)
+    log(f"pool: {len(recipe)} streams, {tot / 1e9:.2f} GB decoded, generated and encoded in "
+        f"{time.perf_counter() - t0:.1f}s on {workers} workers")
+    return res
+
+
+def run_batched(args):
+    """One aceapex_decode_many call over many descriptors vs one aceapex_decode per stream."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2606_04268_amd as ax
+    from paper_2606_04268_amd import _abi
+
+    dev = torch.device("cuda:0")
+    recipe = synth.mix_recipe(args.distinct, 4 << 10, 64 << 20, 0xACE3)
+    pool = build_pool(recipe)
+    rng = np.random.default_rng(0xACE3)
+    pick = rng.integers(0, len(pool), size=args.streams)
+    dss = [ax.to_device(s, dev) for _, s in pool]
+    origs = [torch.from_numpy(x).to(dev) for x, _ in pool]
+    sizes = [dss[i].n for i in pick]
+    offs = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([(n + 255) // 256 * 256 for n in sizes])
+    total = int(sum(sizes))
+    out = torch.empty(max(int(offs[-1]), 256), dtype=torch.uint8, device=dev)
+    outs = [out[int(offs[j]):int(offs[j]) + max(sizes[j], 1)] for j in range(len(sizes))]
+    statuses = torch.zeros(len(sizes), dtype=torch.int32, device=dev)
+    streams = [dss[i] for i in pick]
+    descs = [_abi.Desc(d.abi(), o.data_ptr(), o.numel(), statuses.data_ptr() + 4 * j)
+             for j, (d, o) in enumerate(zip(streams, outs))]
+    ws_bytes = _abi.workspace_bytes(descs)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    log(f"batched: {len(descs)} descriptors over {len(pool)} distinct streams, {total / 1e9:.2f} GB decoded "
+        f"per call, workspace {ws_bytes / 1e9:.2f} GB")
+    stream = torch.cuda.current_stream(dev)
+    single_ws = torch.empty(max(max(ax.workspace_bytes([d]) for d in dss), 256), dtype=torch.uint8, device=dev)
+    single_abi = [d.abi() for d in streams]
+
+    def batched():
+        rc = _abi.decode_many(descs, ws.data_ptr(), ws.numel(), stream.cuda_stream)
+        if rc:
+            raise _abi.AceapexError(rc, "decode_many")
+
+    def loop():
+        for j, a in enumerate(single_abi):
+            rc = _abi.decode(a, outs[j].data_ptr(), outs[j].numel(), single_ws.data_ptr(), single_ws.numel(),
+                             statuses.data_ptr() + 4 * j, stream.cuda_stream)
+            if rc:
+                raise _abi.AceapexError(rc, "decode")
+
+    def verify(label):
+        torch.cuda.synchronize()
+        ax.check_status(statuses)
+        for j, i in enumerate(pick):
+            if not torch.equal(outs[j][:sizes[j]], origs[i]):
+                raise AssertionError(f"{label}: stream {j} differs from its original")
+
+    res = {}
+    for label, fn in (("per_stream_loop", loop), ("batched", batched)):
+        out.fill_(0xA5)
+        statuses.fill_(12345)
+        fn()
+        verify(label)
+        for _ in range(args.warmup):
+            fn()
+        _abi.timing(True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps * 1e3
+        ms = e0.elapsed_time(e1) / args.steps
+        groups = _abi.timing_read()
+        _abi.timing(False)
+        verify(label)
+        res[label] = {"ms_per_call": round(ms, 3), "host_ms_per_call": round(wall, 3),
+                      "gbps": round(total / (ms * 1e-3) / 1e9, 3),
+                      "kernel_groups": {k: {"ms_per_call": round(v[0] / args.steps, 4),
+                                            "launches_per_call": v[1] / args.steps}
+                                        for k, v in groups.items() if v[1]}}
+        log(f"{label}: {ms:.2f} ms per call, {res[label]['gbps']:.1f} GB/s")
+
+    from paper_2606_04268_amd.stats import stream_stats
+
+    st = [stream_stats(s) for _, s in pool]
+    C = sum(st[i]["comp_bytes"] for i in pick)
+    M = sum(st[i]["match_bytes"] for i in pick)
+    b = res["batched"]
+    line = base_line(b["gbps"], args.steps, args.warmup, b["ms_per_call"])
+    line["config"] = {
+        "workload": (f"batched: {len(descs)} streams in one aceapex_decode_many call, sizes log-uniform "
+                     "4 KiB..64 MiB, 40% order-2 Markov text / 40% FASTQ-like (flattened) / 20% random "
+                     f"bytes with 30% repeats; {len(pool)} distinct encoded streams, each descriptor "
+                     "decoding one of them into its own output"),
+        "streams": len(descs), "distinct_streams": len(pool), "decoded_bytes": total, "stream_bytes": C,
+        "match_bytes": M, "matches": int(sum(st[i]["n_seq"] for i in pick)),
+        "max_level": int(max(st[i]["max_level"] for i in pick)),
+    }
+    roof = HBM_PEAK_GBPS * total / (C + total + M)
+    line["bit_exact"] = {"device_compare": True, "statuses_zero": True}
+    line["decode_roofline"] = {"algorithmic_bytes": C + total + M, "decoded_roof_gbps": round(roof, 1),
+                               "frac_of_decoded_roof": round(b["gbps"] / roof, 5)}
+    line["batched"] = b
+    line["per_stream_loop"] = res["per_stream_loop"]
+    line["speedup_vs_loop"] = round(res["per_stream_loop"]["ms_per_call"] / b["ms_per_call"], 3)
+    print(json.dumps(line), flush=True)
+
+
+def run_served(args):
+    """Continuous batching vs one request at a time, over a sweep of offered loads."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2606_04268_amd as ax
+    from paper_2606_04268_amd.serve import Server, poisson_arrivals, summarize
+
+    dev = torch.device("cuda:0")
+    recipe = synth.mix_recipe(64, 64 << 10, 256 << 20, 0xACE4)
+    pool = build_pool(recipe)
+    dss = [ax.to_device(s, dev) for _, s in pool]
+    mean = float(np.mean([d.n for d in dss]))
+    budget = 200 * 10**9
+    srv = Server(dss, budget_bytes=budget, lanes=4, max_batch=256, device=dev)
+    log(f"served: pool of {len(dss)} streams, mean {mean / 1e6:.1f} MB; budget {budget / 1e9:.0f} GB, "
+        f"lane workspace {srv.lane_ws / 1e9:.1f} GB x {len(srv.lanes)}")
+    # warm both paths, and check every pool stream once through the server
+    warm = srv.run([(0.0, i) for i in range(len(dss))], keep_outputs=True)
+    for r in warm:
+        if r.status or not np.array_equal(r.result, pool[r.stream][0]):
+            raise AssertionError(f"served decode of pool stream {r.stream} is not exact")
+    srv.run([(0.0, i) for i in range(4)], mode="fifo")
+    loads = [float(v) for v in args.loads.split(",")]
+    if args.fixed_load not in loads:
+        loads.append(args.fixed_load)
+    sweep = []
+    for li, load in enumerate(sorted(loads)):
+        rate = load * 1e9 / mean
+        count = int(min(20000, max(50, rate * args.seconds)))
+        arr = poisson_arrivals(count, rate, len(dss), seed=0xACE4 + li)
+        row = {"offered_gbps": load, "requests": count}
+        for mode in ("continuous", "fifo"):
+            reqs = srv.run(arr, mode=mode, timeout_s=300)
+            s = summarize(reqs, dss)
+            if s["errors"]:
+                raise AssertionError(f"{s['errors']} served requests failed at {load} GB/s ({mode})")
+            row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
+            log(f"load {load:.0f} GB/s {mode}: p50 {s['p50_ms']:.2f} ms p99 {s['p99_ms']:.2f} ms, "
+                f"{s['aggregate_gbps']:.1f} GB/s over {count} requests")
+        sweep.append(row)
+    fixed = next(r for r in sweep if r["offered_gbps"] == args.fixed_load)
+    c = fixed["continuous"]
+    line = base_line(c["aggregate_gbps"], len(sweep), 1, c["mean_ms"])
+    line["higher_is_better"] = True
+    line["config"] = {
+        "workload": (f"served: Poisson arrivals, sizes log-uniform 64 KiB..256 MiB from {len(dss)} distinct "
+                     "encoded streams of the text / FASTQ-like / random mix, 200 GB device-memory budget, "
+                     "inputs and outputs resident; continuous batching on 4 HIP streams vs one request "
+                     f"at a time; value = decoded GB/s at {args.fixed_load:.0f} GB/s offered"),
+        "budget_bytes": budget, "distinct_streams": len(dss), "mean_request_bytes": round(mean),
+        "arrival_window_s": args.seconds,
+    }
+    line["served_at_fixed_load"] = {"offered_gbps": args.fixed_load, "p50_ms": c["p50_ms"], "p99_ms": c["p99_ms"],
+                                    "fifo_p50_ms": fixed["fifo"]["p50_ms"], "fifo_p99_ms": fixed["fifo"]["p99_ms"],
+                                    "fifo_gbps": fixed["fifo"]["aggregate_gbps"]}
+    line["sweep"] = sweep
+    line["note"] = "steps = number of offered loads; ms_per_step = mean request latency at the fixed load"
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,12 +318,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fastq256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "served"])
+    ap.add_argument("--streams", type=int, default=4096, help="batched: descriptors per call")
+    ap.add_argument("--distinct", type=int, default=256, help="batched: distinct encoded streams")
+    ap.add_argument("--loads", default="10,25,50,100,150,200", help="served: offered GB/s sweep")
+    ap.add_argument("--fixed-load", type=float, default=100.0, help="served: load the line reports")
+    ap.add_argument("--seconds", type=float, default=2.0, help="served: arrival window per load")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "streams are independent, so several GPUs would each decode their own streams "
               "with no communication", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batched":
+        return run_batched(args)
+    if args.mode == "served":
+        return run_served(args)
 
     import numpy as np
     import torch

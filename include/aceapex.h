@@ -54,7 +54,7 @@
  * the output.  The library allocates no device memory on these paths.
  *
  * GPU limits of this version: decoded_bytes and comp_bytes below 2^32,
- * 3 <= block_log2 <= 20, chunk_log2 <= 10, min_match >= 1.
+ * 3 <= block_log2 <= 20, chunk_log2 <= 10, min_match >= 1, n_chunks <= 2^24.
  */
 #ifndef ACEAPEX_H
 #define ACEAPEX_H
@@ -141,8 +141,14 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
 
 /* Decode n independent streams (Sec. 7.5: blocks and streams are independent)
  * as one batch on hip_stream.  h_descs is a host array; the workspace must
- * hold aceapex_workspace_bytes(h_descs, n).  Returns the first synchronous
- * error; per-stream device errors go to each d_status. */
+ * hold aceapex_workspace_bytes(h_descs, n).  When every descriptor carries
+ * h_levels, the streams run as one launch sequence (one setup, one parse over
+ * all their chunks, one launch per level over all their matches); a batch of
+ * more than 2048 streams, or whose match, chunk or block counts would
+ * overflow the 32-bit indexes of one sequence, runs as several consecutive
+ * sequences.  Without the tables the streams are decoded one after the other.
+ * Returns the first synchronous error; per-stream device errors go to each
+ * d_status. */
 int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace,
                         size_t ws_bytes, void *hip_stream);
 

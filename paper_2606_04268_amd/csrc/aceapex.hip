@@ -1,23 +1,26 @@
 // MI355X (gfx950) decoder for absolute-offset LZ77 streams (ACEAPEX,
 // arXiv 2606.04268) behind the C ABI of include/aceapex.h.
 //
-// A decode is a short sequence of launches on the caller's stream, with no
-// host round trip:
+// One stream or a batch of independent streams (Sec. 7.5) is decoded by a
+// short sequence of launches on the caller's stream, with no host round trip:
 //
+//   k_map     (batches) global block and chunk indices -> stream
 //   k_setup   one workgroup per block checks the block table, block header and
 //             chunk index and writes a 48-byte descriptor per chunk (absolute
-//             slices of cmd/len/lvl/lit/off and the output span).  Workgroup 0
-//             also turns the stream's level table (matches per level) into the
-//             first record of every level and clears the counters.
+//             slices of cmd/len/lvl/lit/off and the output span).  The first
+//             workgroups also clear each stream's status and level cursors;
+//             for a single stream, workgroup 0 turns the stream's level table
+//             (matches per level) into the record slots of every level.
 //   k_parse   one workgroup per chunk, four sequences per thread.  When every
 //             cmd/len/lvl value of the chunk is one byte long (the slice length
 //             equals the value count) each thread reads its four values with a
 //             single 4-byte load per stream; otherwise three waves decode the
 //             LEB128 slices into LDS first.  A workgroup scan turns run and
-//             match lengths into output and literal offsets, each thread
-//             copies its literal runs to their places (Sec. 3.2), and every
-//             match becomes a 12-byte record (dst, src, len) in the bucket of
-//             its level.
+//             match lengths into output and literal offsets.  The literal runs
+//             are placed in an LDS image of the chunk's output span, which is
+//             written with aligned 16-byte stores (Sec. 3.2); every match
+//             becomes a 12-byte record (dst, src, len | stream << 21) in the
+//             slots of its level.
 //   k_level   one launch per level k (Sec. 7.1): the copies of level k read
 //             only bytes written by literals or by lower levels and are
 //             independent of each other, so every thread simply runs four
@@ -25,8 +28,13 @@
 //   k_tail    the deep levels that hold few matches run in a single workgroup,
 //             level after level, separated by workgroup barriers: one CU, so
 //             no cache maintenance between levels.
+//
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// their index; k_parse and k_level hand each XCD one contiguous range of
+// chunks / records so that neighbouring work shares an L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -45,10 +53,15 @@ constexpr uint32_t PER = K_MAX / NT;        // sequences per thread in k_parse
 constexpr uint32_t LH = 256;                // levels bucketed through LDS; deeper ones use global atomics
 constexpr uint32_t HDR = 64, BLKHDR = 32, CHUNK_ENT = 32;
 constexpr uint32_t BLOCK_LOG2_MAX = 20;
+constexpr uint32_t LEN_BITS = 21;           // a match length needs 21 bits (blocks of at most 2^20 bytes)
+constexpr uint32_t LEN_MASK = (1u << LEN_BITS) - 1;
+constexpr uint32_t JOBS_MAX = 1u << (32 - LEN_BITS);  // streams per launch sequence
 constexpr uint32_t ROUND = 4;               // records per thread per round of k_level / k_tail
 constexpr uint32_t LONG_COPY = 128;         // matches longer than this are copied by a whole wave
 constexpr uint32_t LEVEL_WG_MAX = 2048;     // workgroups of one level launch, at most
 constexpr uint32_t TAIL_LEVEL_MAX = 8192;   // levels with at most this many matches may join the tail
+constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
+constexpr uint64_t CHUNKS_MAX = 1ull << 24;  // chunks of one launch sequence (the k_parse grid), at most
 
 typedef uint16_t u16u __attribute__((aligned(1)));
 typedef uint32_t u32u __attribute__((aligned(1)));
@@ -56,7 +69,7 @@ typedef uint64_t u64u __attribute__((aligned(1)));
 struct __attribute__((aligned(1))) u128u { uint32_t a, b, c, d; };
 
 struct ChunkDesc {
-    uint32_t out_base, out_len;   // absolute output span of the chunk
+    uint32_t out_base, out_len;   // output span of the chunk, relative to its stream's output
     uint32_t cmd_at, cmd_n;       // byte slices inside the compressed stream
     uint32_t len_at, len_n;
     uint32_t lvl_at, lvl_n;
@@ -66,21 +79,32 @@ struct ChunkDesc {
 };
 static_assert(sizeof(ChunkDesc) == 48, "descriptor layout");
 
+// One stream as the kernels see it.
 struct Job {
     const uint8_t *comp;
     uint8_t *out;
+    int32_t *status;
+    ChunkDesc *chunks;   // [n_chunks]
+    uint8_t *blk_ok;     // [n_blocks] 1 when the block passed the checks of k_setup
     uint32_t n, comp_bytes;
     uint32_t n_blocks, block_log2, min_match, chunk_log2;
     uint32_t max_level, n_chunks, n_seq;
-    ChunkDesc *chunks;   // [n_chunks]
-    uint8_t *blk_ok;     // [n_blocks] 1 when the block passed the checks of k_setup
-    uint32_t *rec_base;  // [max_level + 2] first record of each level
-    uint32_t *cursor;    // [max_level + 1] next free record of each level (without block cursors)
-    uint32_t *bcount;    // [(max_level + 1) * n_blocks] matches per (level, block)
-    uint32_t *bcursor;   // [(max_level + 1) * n_blocks] next free record per (level, block)
-    uint32_t use_bcur;   // records are reserved per (level, block) rather than per level
-    uint32_t *recs;      // [3 * n_seq] (dst, src, len)
-    int32_t *status;
+    uint32_t c0, b0;     // first global chunk and block of the stream in its batch
+    uint32_t lv0;        // first entry of the stream in the per-(stream, level) arrays
+};
+
+// A decode: one stream (jobs == nullptr) or a batch of streams.
+struct Batch {
+    Job one;                    // the stream of a single-stream decode
+    const Job *jobs;            // device table of a batched decode, or nullptr
+    uint32_t *blk_job;          // [n_blocks] global block -> stream (batched)
+    uint32_t *chunk_job;        // [n_chunks] global chunk -> stream (batched)
+    uint32_t *rec_lo, *rec_hi;  // per (stream, level): record slots [rec_lo, rec_hi)
+    uint32_t *cursor;           // per (stream, level): next free slot
+    const uint32_t *level_lo;   // [max_level + 2] slots of each level over the batch (batched)
+    uint32_t *recs;             // 3 u32 per match: dst, src, len | stream << LEN_BITS
+    uint32_t n_jobs, n_blocks, n_chunks, max_level;  // totals over the batch, highest level
+    uint32_t n_seq;             // matches over the batch
 };
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
@@ -94,6 +118,8 @@ __device__ __forceinline__ uint32_t xcd_slot(uint32_t i, uint32_t G)
     const uint32_t x = i % P, k = i / P, q = G / P, r = G % P;
     return x * q + min(x, r) + k;
 }
+
+__device__ __forceinline__ const Job &job_of(const Batch &B, uint32_t s) { return B.jobs ? B.jobs[s] : B.one; }
 
 __device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *(const u32u *)p; }
 __device__ __forceinline__ uint64_t ld64(const uint8_t *p) { return *(const u64u *)p; }
@@ -138,36 +164,37 @@ __device__ __forceinline__ void wave_copy(uint8_t *d, const uint8_t *s, uint32_t
     for (uint32_t o = lane * 16; o < n; o += 64 * 16) copy_bytes(d + o, s + o, min(16u, n - o));
 }
 
-// Run up to ROUND match records held by this thread.  Matches of at most 16
-// bytes take one 16-byte load of their source (when 16 bytes are there to
-// read: bytes past the match are read and discarded) and exact stores; all
-// loads of the round are issued before the stores.  Longer matches are then
-// copied by the whole wave, one at a time.
-__device__ __forceinline__ void run_records(const Job &j, const uint32_t *dst, const uint32_t *src,
-                                            uint32_t *len, bool &bad)
+// Run up to ROUND match records held by this thread, each into its own
+// stream's output ob[u] of on[u] bytes.  Matches of at most 16 bytes take one
+// 16-byte load of their source (when 16 bytes are there to read: bytes past
+// the match are read and discarded) and exact stores; all loads of the round
+// are issued before the stores.  Longer matches are then copied by the whole
+// wave, one at a time.
+__device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *on, int32_t *const *sp,
+                                            const uint32_t *dst, const uint32_t *src, uint32_t *len)
 {
     uint64_t lo[ROUND], hi[ROUND];
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
-        if (len[u] && ((uint64_t)dst[u] + len[u] > j.n || (uint64_t)src[u] + len[u] > dst[u])) {
-            bad = true;
+        if (len[u] && ((uint64_t)dst[u] + len[u] > on[u] || (uint64_t)src[u] + len[u] > dst[u])) {
+            atomicCAS(sp[u], 0, ACEAPEX_E_CORRUPT);
             len[u] = 0;
         }
-        const bool small = len[u] && len[u] <= 16 && (uint64_t)src[u] + 16 <= j.n;
-        const uint8_t *p = j.out + (small ? src[u] : 0u);
+        const bool small = len[u] && len[u] <= 16 && (uint64_t)src[u] + 16 <= on[u];
         lo[u] = 0; hi[u] = 0;
-        if (small || j.n >= 16) {
-            lo[u] = ld64(p);
-            hi[u] = ld64(p + 8);
+        if (small) {
+            const u128u v = *(const u128u *)(ob[u] + src[u]);
+            lo[u] = ((uint64_t)v.b << 32) | v.a;
+            hi[u] = ((uint64_t)v.d << 32) | v.c;
         }
     }
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
         if (!len[u]) continue;
-        if (len[u] <= 16 && (uint64_t)src[u] + 16 <= j.n) {
-            store_upto16(j.out + dst[u], lo[u], hi[u], len[u]);
+        if (len[u] <= 16 && (uint64_t)src[u] + 16 <= on[u]) {
+            store_upto16(ob[u] + dst[u], lo[u], hi[u], len[u]);
         } else if (len[u] <= LONG_COPY) {
-            copy_bytes(j.out + dst[u], j.out + src[u], len[u]);
+            copy_bytes(ob[u] + dst[u], ob[u] + src[u], len[u]);
         }
     }
 #pragma unroll
@@ -178,25 +205,83 @@ __device__ __forceinline__ void run_records(const Job &j, const uint32_t *dst, c
             m &= m - 1;
             const uint32_t d0 = __shfl(dst[u], lane, 64), s0 = __shfl(src[u], lane, 64);
             const uint32_t n0 = __shfl(len[u], lane, 64);
-            wave_copy(j.out + d0, j.out + s0, n0);
+            uint8_t *o = (uint8_t *)__shfl((unsigned long long)(uintptr_t)ob[u], lane, 64);
+            wave_copy(o + d0, o + s0, n0);
         }
     }
 }
 
-// Load ROUND records r0, r0 + stride, ... (those below r_end) without
-// waiting between them.
-__device__ __forceinline__ void load_records(const Job &j, uint32_t r0, uint32_t stride, uint32_t r_end,
-                                             uint32_t *dst, uint32_t *src, uint32_t *len)
+// Slots [lo, hi) of level k: in a single-stream decode the filled part of the
+// level; in a batch the level's slots over all streams (unfilled slots are
+// rejected record by record).
+__device__ __forceinline__ void level_range(const Batch &B, uint32_t k, uint32_t &lo, uint32_t &hi)
+{
+    if (B.jobs) {
+        lo = B.level_lo[k];
+        hi = B.level_lo[k + 1];
+    } else {
+        lo = B.rec_lo[k];
+        hi = min(B.cursor[k], B.rec_hi[k]);
+    }
+}
+
+// Raw words of the records r0 + u*stride (u < ROUND), without waiting
+// between them; a slot at or past r_end gets lj = 0 (no match).
+__device__ __forceinline__ void fetch_records(const Batch &B, uint32_t r0, uint32_t stride, uint32_t r_end,
+                                              uint32_t *dst, uint32_t *src, uint32_t *lj)
 {
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
         const uint32_t i = r0 + u * stride;
         const bool ok = i < r_end;
-        const uint32_t *r = j.recs + 3ull * (ok ? i : r0);
+        const uint32_t *r = B.recs + 3ull * (ok ? i : r0);
         dst[u] = r[0];
         src[u] = r[1];
-        len[u] = ok ? r[2] : 0u;
+        lj[u] = ok ? r[2] : 0u;
     }
+}
+
+// The stream of each fetched record: its output, size and status; a record
+// in a slot that a batched stream did not fill in this decode yields len = 0.
+__device__ __forceinline__ void resolve_records(const Batch &B, uint32_t k, uint32_t r0, uint32_t stride,
+                                                const uint32_t *lj, uint8_t **ob, uint32_t *on, int32_t **sp,
+                                                uint32_t *len)
+{
+#pragma unroll
+    for (uint32_t u = 0; u < ROUND; u++) {
+        const uint32_t i = r0 + u * stride;
+        len[u] = lj[u] & LEN_MASK;
+        if (!B.jobs) {
+            ob[u] = B.one.out;
+            on[u] = B.one.n;
+            sp[u] = B.one.status;
+        } else {
+            const uint32_t s = lj[u] >> LEN_BITS;
+            ob[u] = nullptr;
+            on[u] = 0;
+            sp[u] = nullptr;
+            if (len[u] && s < B.n_jobs) {
+                const Job &j = B.jobs[s];
+                const uint32_t e = j.lv0 + k;
+                if (k <= j.max_level && i >= B.rec_lo[e] && i < min(B.cursor[e], B.rec_hi[e])) {
+                    ob[u] = j.out;
+                    on[u] = j.n;
+                    sp[u] = j.status;
+                }
+            }
+            if (!ob[u]) len[u] = 0;
+        }
+    }
+}
+
+// Fetch and resolve ROUND records (see fetch_records, resolve_records).
+__device__ __forceinline__ void load_records(const Batch &B, uint32_t k, uint32_t r0, uint32_t stride,
+                                             uint32_t r_end, uint8_t **ob, uint32_t *on, int32_t **sp,
+                                             uint32_t *dst, uint32_t *src, uint32_t *len)
+{
+    uint32_t lj[ROUND];
+    fetch_records(B, r0, stride, r_end, dst, src, lj);
+    resolve_records(B, k, r0, stride, lj, ob, on, sp, len);
 }
 
 // ------------------------------------------------------------------- scans
@@ -293,23 +378,52 @@ __device__ bool wave_varints(const uint8_t *p, uint32_t nb, uint32_t cnt, uint32
     return __ballot(!ok) == 0;
 }
 
+// Descriptor checks that keep every access of the chunk inside the stream
+// and the output, whatever the workspace held before.
+__device__ __forceinline__ bool desc_in_bounds(const Job &j, const ChunkDesc &d, uint32_t K)
+{
+    const uint32_t ns = d.nseq_last & 0x7fffffffu;
+    return ns <= K && (uint64_t)d.out_base + d.out_len <= j.n &&
+           (uint64_t)d.cmd_at + d.cmd_n <= j.comp_bytes && d.cmd_n <= 4 * (ns + 1) &&
+           (uint64_t)d.len_at + d.len_n <= j.comp_bytes && d.len_n <= 4 * ns &&
+           (uint64_t)d.lvl_at + d.lvl_n <= j.comp_bytes && d.lvl_n <= 4 * ns &&
+           (uint64_t)d.lit_at + d.lit_n <= j.comp_bytes && (uint64_t)d.off_at + 4ull * ns <= j.comp_bytes;
+}
+
+// The 4 bytes of a one-byte-per-value slice that belong to values [e, e+4),
+// zero past the slice's count.
+__device__ __forceinline__ uint32_t bytes4(const uint8_t *p, uint32_t e, uint32_t cnt)
+{
+    if (e + 4 <= cnt) return ld32(p + e);
+    uint32_t v = 0;
+    for (uint32_t k = 0; k < 4; k++)
+        if (e + k < cnt) v |= (uint32_t)p[e + k] << (8 * k);
+    return v;
+}
+
+// --------------------------------------------------------------- k_map
+
+// Batches: global block / chunk index -> stream.
+__global__ void __launch_bounds__(NT) k_map(Batch B)
+{
+    const Job &j = B.jobs[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < j.n_blocks; i += NT) B.blk_job[j.b0 + i] = blockIdx.x;
+    for (uint32_t i = threadIdx.x; i < j.n_chunks; i += NT) B.chunk_job[j.c0 + i] = blockIdx.x;
+}
+
 // --------------------------------------------------------------- k_setup
 
-__global__ void __launch_bounds__(NT) k_setup(Job j)
+__global__ void __launch_bounds__(NT) k_setup(Batch B)
 {
     __shared__ uint32_t ok_blk;
     __shared__ uint64_t tmp[NT / 64];
-    __shared__ uint32_t hist[LH];
-    __shared__ uint32_t vals[NT / 64][K_MAX];
     const uint32_t t = threadIdx.x;
-    const uint64_t B = (uint64_t)1 << j.block_log2;
-    const uint32_t K = 1u << j.chunk_log2;
-    const uint64_t lvl_tab = HDR + 16ull * (j.n_blocks + 1);
-    const uint64_t prefix = lvl_tab + pad16(4ull * (j.max_level + 1));
 
-    if (blockIdx.x == 0) {
-        // level table -> first record of every level
+    if (!B.jobs && blockIdx.x == 0) {
+        // single stream: its level table -> record slots of every level
+        const Job &j = B.one;
         if (t == 0) *j.status = 0;
+        const uint64_t lvl_tab = HDR + 16ull * (j.n_blocks + 1);
         uint64_t carry = 0;
         for (uint32_t s = 0; s <= j.max_level; s += NT) {
             const uint32_t i = s + t;
@@ -317,19 +431,28 @@ __global__ void __launch_bounds__(NT) k_setup(Job j)
             uint64_t tot;
             const uint64_t ex = wg_excl_scan64(c, tmp, tot);
             if (i <= j.max_level) {
-                const uint32_t rb = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
-                j.rec_base[i] = rb;
-                j.cursor[i] = rb;
+                const uint32_t lo = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
+                B.rec_lo[i] = lo;
+                B.cursor[i] = lo;
+                B.rec_hi[i] = (uint32_t)min(carry + ex + c, (uint64_t)j.n_seq);
             }
             carry += tot;
         }
-        if (t == 0) {
-            j.rec_base[j.max_level + 1] = (uint32_t)min(carry, (uint64_t)j.n_seq);
-            if (carry != j.n_seq) fail(j, ACEAPEX_E_CORRUPT);  // every match counted exactly once
-        }
+        if (t == 0 && carry != j.n_seq) fail(j, ACEAPEX_E_CORRUPT);  // every match counted exactly once
+    }
+    if (B.jobs && blockIdx.x < B.n_jobs) {
+        // batch: clear this stream's status and level cursors (slots were laid out on the host)
+        const Job &j = B.jobs[blockIdx.x];
+        if (t == 0) *j.status = 0;
+        for (uint32_t i = t; i <= j.max_level; i += NT) B.cursor[j.lv0 + i] = B.rec_lo[j.lv0 + i];
     }
 
-    for (uint32_t b = blockIdx.x; b < j.n_blocks; b += gridDim.x) {
+    for (uint32_t gb = blockIdx.x; gb < B.n_blocks; gb += gridDim.x) {
+        const Job &j = job_of(B, B.jobs ? B.blk_job[gb] : 0u);
+        const uint32_t b = gb - j.b0;
+        const uint64_t Bsz = (uint64_t)1 << j.block_log2;
+        const uint32_t K = 1u << j.chunk_log2;
+        const uint64_t prefix = HDR + 16ull * (j.n_blocks + 1) + pad16(4ull * (j.max_level + 1));
         const uint8_t *tb = j.comp + HDR + 16ull * b;
         const uint64_t o0 = ld64(tb), o1 = ld64(tb + 16);
         const uint32_t sb0 = ld32(tb + 8), cb0 = ld32(tb + 12), sb1 = ld32(tb + 24), cb1 = ld32(tb + 28);
@@ -361,7 +484,7 @@ __global__ void __launch_bounds__(NT) k_setup(Job j)
             if (t == 0) j.blk_ok[b] = 0;
             continue;
         }
-        const uint32_t blen = (uint32_t)min(B, (uint64_t)j.n - b * B);
+        const uint32_t blen = (uint32_t)min(Bsz, (uint64_t)j.n - b * Bsz);
         bool all = true;
         for (uint32_t c = t; c < nc; c += NT) {
             const uint8_t *e = j.comp + o0 + BLKHDR + (uint64_t)CHUNK_ENT * c;
@@ -374,7 +497,7 @@ __global__ void __launch_bounds__(NT) k_setup(Job j)
                              q0 <= q1 && q1 <= nl && d0 <= d1 && d1 <= blen &&
                              c1 - c0 <= 4 * (n_in + 1) && l1 - l0 <= 4 * n_in && v1 - v0 <= 4 * n_in;
             ChunkDesc cd;
-            cd.out_base = (uint32_t)(b * B) + d0;
+            cd.out_base = (uint32_t)(b * Bsz) + d0;
             cd.out_len = d1 - d0;
             cd.cmd_at = (uint32_t)cmd_at + c0; cd.cmd_n = c1 - c0;
             cd.len_at = (uint32_t)len_at + l0; cd.len_n = l1 - l0;
@@ -392,64 +515,7 @@ __global__ void __launch_bounds__(NT) k_setup(Job j)
         __syncthreads();
         if (!all) ok_blk = 0;
         __syncthreads();
-        if (j.use_bcur && ok_blk) {
-            // matches of this block at every level, for the per-(level, block) record ranges
-            const uint32_t nh = min(j.max_level + 1, LH);
-            for (uint32_t i = t; i < nh; i += NT) hist[i] = 0;
-            for (uint32_t i = LH + t; i <= j.max_level; i += NT) j.bcount[(uint64_t)i * j.n_blocks + b] = 0;
-            __syncthreads();
-            bool vok = true;
-            if (lvlb == ns) {  // one byte per level
-                for (uint32_t i = t; i < ns; i += NT) {
-                    const uint32_t l = j.comp[lvl_at + i];
-                    if (l > j.max_level || (l & 0x80)) vok = false;
-                    else if (l < LH) atomicAdd(&hist[l], 1u);
-                    else atomicAdd(&j.bcount[(uint64_t)l * j.n_blocks + b], 1u);
-                }
-            } else {  // LEB128: one wave per chunk, through the chunk index
-                const uint32_t w = t >> 6;
-                for (uint32_t c = w; c < nc; c += NT / 64) {
-                    const uint8_t *e = j.comp + o0 + BLKHDR + (uint64_t)CHUNK_ENT * c;
-                    const uint32_t v0 = ld32(e + 8), v1 = c + 1 < nc ? ld32(e + 40) : lvlb;
-                    const uint32_t n_in = min(K, ns - c * K);
-                    if (!wave_varints(j.comp + lvl_at + v0, v1 - v0, n_in, vals[w])) {
-                        vok = false;
-                        continue;
-                    }
-                    for (uint32_t i = t & 63; i < n_in; i += 64) {
-                        const uint32_t l = vals[w][i];
-                        if (l > j.max_level) vok = false;
-                        else if (l < LH) atomicAdd(&hist[l], 1u);
-                        else atomicAdd(&j.bcount[(uint64_t)l * j.n_blocks + b], 1u);
-                    }
-                }
-            }
-            if (!vok) ok_blk = 0;
-            __syncthreads();
-            for (uint32_t i = t; i < nh; i += NT) j.bcount[(uint64_t)i * j.n_blocks + b] = hist[i];
-        }
         if (t == 0) j.blk_ok[b] = (uint8_t)ok_blk;
-        __syncthreads();
-    }
-}
-
-// Per level l (one workgroup each): first record of every block's share of
-// the level, from the per-(level, block) counts.
-__global__ void __launch_bounds__(NT) k_bscan(Job j)
-{
-    __shared__ uint64_t tmp[NT / 64];
-    for (uint32_t l = blockIdx.x; l <= j.max_level; l += gridDim.x) {
-        const uint64_t row = (uint64_t)l * j.n_blocks;
-        uint64_t carry = j.rec_base[l];
-        for (uint32_t s = 0; s < j.n_blocks; s += NT) {
-            const uint32_t b = s + threadIdx.x;
-            const uint32_t c = b < j.n_blocks ? j.bcount[row + b] : 0;
-            uint64_t tot;
-            const uint64_t ex = wg_excl_scan64(c, tmp, tot);
-            if (b < j.n_blocks) j.bcursor[row + b] = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
-            carry += tot;
-        }
-        if (threadIdx.x == 0 && carry != j.rec_base[l + 1]) fail(j, ACEAPEX_E_CORRUPT);
         __syncthreads();
     }
 }
@@ -457,54 +523,41 @@ __global__ void __launch_bounds__(NT) k_bscan(Job j)
 // --------------------------------------------------------------- k_parse
 
 struct ParseLds {
-    uint32_t run[K_MAX + 1];     // LEB128 path: literal runs
-    uint32_t mlen[K_MAX];        // LEB128 path: match lengths - min_match
-    uint32_t lvl[K_MAX];         // LEB128 path: match levels
+    union {
+        struct {
+            uint32_t run[K_MAX + 1];   // LEB128 path: literal runs
+            uint32_t mlen[K_MAX];      // LEB128 path: match lengths - min_match
+            uint32_t lvl[K_MAX];       // LEB128 path: match levels
+        } v;
+        uint8_t tile[TILE_BYTES];      // after the scan: the chunk's output span, literals in place
+    } u;
     uint32_t lcount[LH];         // matches of the chunk per level (levels < LH)
     uint32_t lbase[LH];          // record slot reserved for them
     uint64_t tmp[NT / 64];
     uint32_t bad;
-};
+} __attribute__((aligned(16)));
 
-// Descriptor checks that keep every access of the chunk inside the stream
-// and the output, whatever the workspace held before.
-__device__ __forceinline__ bool desc_in_bounds(const Job &j, const ChunkDesc &d, uint32_t K)
-{
-    const uint32_t ns = d.nseq_last & 0x7fffffffu;
-    return ns <= K && (uint64_t)d.out_base + d.out_len <= j.n &&
-           (uint64_t)d.cmd_at + d.cmd_n <= j.comp_bytes && d.cmd_n <= 4 * (ns + 1) &&
-           (uint64_t)d.len_at + d.len_n <= j.comp_bytes && d.len_n <= 4 * ns &&
-           (uint64_t)d.lvl_at + d.lvl_n <= j.comp_bytes && d.lvl_n <= 4 * ns &&
-           (uint64_t)d.lit_at + d.lit_n <= j.comp_bytes && (uint64_t)d.off_at + 4ull * ns <= j.comp_bytes;
-}
-
-// The 4 bytes of a one-byte-per-value slice that belong to values [e, e+4),
-// zero past the slice's count.
-__device__ __forceinline__ uint32_t bytes4(const uint8_t *p, uint32_t e, uint32_t cnt)
-{
-    if (e + 4 <= cnt) return ld32(p + e);
-    uint32_t v = 0;
-    for (uint32_t k = 0; k < 4; k++)
-        if (e + k < cnt) v |= (uint32_t)p[e + k] << (8 * k);
-    return v;
-}
-
-__global__ void __launch_bounds__(NT) k_parse(Job j)
+__global__ void __launch_bounds__(NT) k_parse(Batch B)
 {
     __shared__ ParseLds L;
     const uint32_t t = threadIdx.x, wave = t >> 6;
+    const uint32_t g = xcd_slot(blockIdx.x, gridDim.x);  // global chunk
+    const uint32_t sj = B.jobs ? B.chunk_job[g] : 0u;    // its stream
+    const Job &j = job_of(B, sj);
+    const uint32_t c = g - j.c0;
     const uint32_t K = 1u << j.chunk_log2;
     const uint32_t nl = min(j.max_level + 1, LH);
 
-    if (blockIdx.x == 0) {  // any block that failed its checks fails the decode
+    if (c == 0) {  // any block of the stream that failed its checks fails the stream
         bool bad = false;
         for (uint32_t b = t; b < j.n_blocks; b += NT) bad |= j.blk_ok[b] == 0;
         if (bad) fail(j, ACEAPEX_E_CORRUPT);
     }
-    const ChunkDesc d = j.chunks[xcd_slot(blockIdx.x, gridDim.x)];
     if (t == 0) L.bad = 0;
     for (uint32_t i = t; i < nl; i += NT) L.lcount[i] = 0;
     __syncthreads();
+    if (c >= j.n_chunks) return;
+    const ChunkDesc d = j.chunks[c];
     const uint32_t blk = d.out_base >> j.block_log2;
     if (!desc_in_bounds(j, d, K) || blk >= j.n_blocks) {
         if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
@@ -537,9 +590,9 @@ __global__ void __launch_bounds__(NT) k_parse(Job j)
         }
     } else {
         bool ok = true;
-        if (wave == 0) ok = wave_varints(j.comp + d.cmd_at, d.cmd_n, ncmd, L.run);
-        else if (wave == 1) ok = wave_varints(j.comp + d.len_at, d.len_n, ns, L.mlen);
-        else if (wave == 2) ok = wave_varints(j.comp + d.lvl_at, d.lvl_n, ns, L.lvl);
+        if (wave == 0) ok = wave_varints(j.comp + d.cmd_at, d.cmd_n, ncmd, L.u.v.run);
+        else if (wave == 1) ok = wave_varints(j.comp + d.len_at, d.len_n, ns, L.u.v.mlen);
+        else if (wave == 2) ok = wave_varints(j.comp + d.lvl_at, d.lvl_n, ns, L.u.v.lvl);
         if (!ok && (t & 63) == 0) L.bad = 1;
         __syncthreads();
         if (L.bad) {
@@ -549,9 +602,9 @@ __global__ void __launch_bounds__(NT) k_parse(Job j)
 #pragma unroll
         for (uint32_t u = 0; u < PER; u++) {
             const uint32_t e = e0 + u;
-            r[u] = e < ncmd ? L.run[e] : 0;
-            m[u] = e < ns ? L.mlen[e] + j.min_match : 0;
-            l[u] = e < ns ? L.lvl[e] : 0;
+            r[u] = e < ncmd ? L.u.v.run[e] : 0;
+            m[u] = e < ns ? L.u.v.mlen[e] + j.min_match : 0;
+            l[u] = e < ns ? L.u.v.lvl[e] : 0;
         }
     }
 
@@ -571,19 +624,56 @@ __global__ void __launch_bounds__(NT) k_parse(Job j)
         return;
     }
 
-    // literal runs to their output positions; destinations of the matches
+    // Literal runs to their output positions.  When the chunk's output span
+    // fits the LDS tile, the runs are placed in the tile and the whole span is
+    // written with aligned 16-byte stores (its match bytes are written later by
+    // the level launches); otherwise every run is copied on its own.
+    const uint32_t base16 = d.out_base & ~15u;
+    const uint32_t span_end = d.out_base + d.out_len;
+    const bool tiled = span_end - base16 <= TILE_BYTES;
     uint32_t pos = d.out_base + (uint32_t)(ex >> 32), lq = (uint32_t)ex;
     uint32_t dst[PER], rank[PER];
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
-        if (r[u]) copy_bytes(j.out + pos, j.comp + d.lit_at + lq, r[u]);
+        if (r[u]) {
+            const uint8_t *ls = j.comp + d.lit_at + lq;
+            if (!tiled) {
+                copy_bytes(j.out + pos, ls, r[u]);
+            } else {
+                uint8_t *td = L.u.tile + (pos - base16);
+                for (uint32_t o = 0; o < r[u]; o += 16) {
+                    const uint32_t n = min(16u, r[u] - o);
+                    if ((uint64_t)(d.lit_at + lq + o) + 16 <= j.comp_bytes) {
+                        const u128u v = *(const u128u *)(ls + o);
+                        store_upto16(td + o, ((uint64_t)v.b << 32) | v.a, ((uint64_t)v.d << 32) | v.c, n);
+                    } else {
+                        for (uint32_t k = 0; k < n; k++) td[o + k] = ls[o + k];
+                    }
+                }
+            }
+        }
         pos += r[u];
         lq += r[u];
         dst[u] = pos;
         pos += m[u];
     }
+    if (tiled) {
+        __syncthreads();
+        const uint32_t nseg = (span_end - base16 + 15) / 16;
+        for (uint32_t i = t; i < nseg; i += NT) {
+            const uint32_t a = base16 + 16 * i;
+            const uint8_t *tsrc = L.u.tile + 16 * i;
+            if (a >= d.out_base && a + 16 <= span_end) {
+                *(uint4 *)(j.out + a) = *(const uint4 *)tsrc;
+            } else {
+                for (uint32_t k = 0; k < 16; k++)
+                    if (a + k >= d.out_base && a + k < span_end) j.out[a + k] = tsrc[k];
+            }
+        }
+    }
 
-    // every match -> record in the bucket of its level
+    // every match -> record in the slots of its level
+    const uint32_t tag = sj << LEN_BITS;
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
         rank[u] = 0xffffffffu;
@@ -595,11 +685,11 @@ __global__ void __launch_bounds__(NT) k_parse(Job j)
         if (l[u] < LH) {
             rank[u] = atomicAdd(&L.lcount[l[u]], 1u);
         } else {
-            const uint32_t slot = atomicAdd(j.use_bcur ? &j.bcursor[(uint64_t)l[u] * j.n_blocks + blk]
-                                                       : &j.cursor[l[u]], 1u);
-            if (slot < j.rec_base[l[u] + 1]) {
-                uint32_t *rr = j.recs + 3ull * slot;
-                rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u];
+            const uint32_t e = j.lv0 + l[u];
+            const uint32_t slot = atomicAdd(&B.cursor[e], 1u);
+            if (slot < B.rec_hi[e]) {
+                uint32_t *rr = B.recs + 3ull * slot;
+                rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u] | tag;
             } else {
                 bad = true;
             }
@@ -607,62 +697,78 @@ __global__ void __launch_bounds__(NT) k_parse(Job j)
     }
     __syncthreads();
     for (uint32_t i = t; i < nl; i += NT)
-        if (L.lcount[i])
-            L.lbase[i] = atomicAdd(j.use_bcur ? &j.bcursor[(uint64_t)i * j.n_blocks + blk] : &j.cursor[i],
-                                   L.lcount[i]);
+        if (L.lcount[i]) L.lbase[i] = atomicAdd(&B.cursor[j.lv0 + i], L.lcount[i]);
     __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
         if (rank[u] == 0xffffffffu) continue;
         const uint32_t slot = L.lbase[l[u]] + rank[u];
-        if (slot >= j.rec_base[l[u] + 1]) {  // more matches than the level table announced
+        if (slot >= B.rec_hi[j.lv0 + l[u]]) {  // more matches than the level table announced
             bad = true;
             continue;
         }
-        uint32_t *rr = j.recs + 3ull * slot;
-        rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u];
+        uint32_t *rr = B.recs + 3ull * slot;
+        rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u] | tag;
     }
     if (bad) fail(j, ACEAPEX_E_CORRUPT);
 }
 
 // --------------------------------------------------------------- k_level
 
-// The level's records are split into one contiguous part per XCD; the
+// The level's slots are split into one contiguous part per XCD; the
 // workgroups of an XCD sweep its part together, tile after tile, so that the
-// destinations and in-block sources they touch at one time share its L2.
-__global__ void __launch_bounds__(NT) k_level(Job j, uint32_t k)
+// destinations and sources they touch at one time share its L2.
+__global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
 {
-    const uint32_t R0 = j.rec_base[k];
-    const uint32_t R1 = j.use_bcur ? j.rec_base[k + 1] : min(j.cursor[k], j.rec_base[k + 1]);
+    uint32_t R0, R1;
+    level_range(B, k, R0, R1);
     const uint32_t G = gridDim.x, P = G < 8 ? G : 8;
     const uint32_t x = blockIdx.x % P, w = blockIdx.x / P, W = (G - x + P - 1) / P;
     const uint64_t S = R1 > R0 ? R1 - R0 : 0;
     const uint32_t p0 = R0 + (uint32_t)(S * x / P), p1 = R0 + (uint32_t)(S * (x + 1) / P);
-    bool bad = false;
     for (uint32_t r0 = p0 + w * (NT * ROUND) + threadIdx.x;; r0 += W * (NT * ROUND)) {
         if (__ballot(r0 < p1) == 0) break;
-        uint32_t dst[ROUND], src[ROUND], len[ROUND];
-        load_records(j, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, dst, src, len);
-        run_records(j, dst, src, len, bad);
+        uint8_t *ob[ROUND];
+        int32_t *sp[ROUND];
+        uint32_t on[ROUND], dst[ROUND], src[ROUND], len[ROUND];
+        load_records(B, k, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
+        run_records(ob, on, sp, dst, src, len);
     }
-    if (bad) fail(j, ACEAPEX_E_CORRUPT);
 }
 
-// The tail of deep levels [k0, max_level] in one workgroup of NT_TAIL threads.
-__global__ void __launch_bounds__(NT_TAIL) k_tail(Job j, uint32_t k0)
+// The tail of deep levels [k0, max_level] in one workgroup of NT_TAIL
+// threads.  The first round of the next level's records is fetched before the
+// current level's copies, so that after each barrier only the source reads
+// remain.
+__global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
 {
-    bool bad = false;
-    for (uint32_t k = k0; k <= j.max_level; k++) {
-        const uint32_t r_end = j.use_bcur ? j.rec_base[k + 1] : min(j.cursor[k], j.rec_base[k + 1]);
-        for (uint32_t r0 = j.rec_base[k] + threadIdx.x;; r0 += ROUND * NT_TAIL) {
-            if (__ballot(r0 < r_end) == 0) break;
-            uint32_t dst[ROUND], src[ROUND], len[ROUND];
-            load_records(j, min(r0, r_end - 1), NT_TAIL, r0 < r_end ? r_end : 0, dst, src, len);
-            run_records(j, dst, src, len, bad);
+    uint32_t nd[ROUND], nsr[ROUND], nlj[ROUND];
+    uint32_t lo, hi;
+    level_range(B, k0, lo, hi);
+    fetch_records(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd, nsr, nlj);
+    for (uint32_t k = k0; k <= B.max_level; k++) {
+        const uint32_t lo_k = lo, hi_k = hi;
+        uint32_t dst[ROUND], src[ROUND], lj[ROUND];
+#pragma unroll
+        for (uint32_t u = 0; u < ROUND; u++) { dst[u] = nd[u]; src[u] = nsr[u]; lj[u] = nlj[u]; }
+        if (k < B.max_level) {
+            level_range(B, k + 1, lo, hi);
+            fetch_records(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd,
+                          nsr, nlj);
+        }
+        uint8_t *ob[ROUND];
+        int32_t *sp[ROUND];
+        uint32_t on[ROUND], len[ROUND];
+        const uint32_t r0 = hi_k ? min(lo_k + threadIdx.x, hi_k - 1) : 0;
+        resolve_records(B, k, r0, NT_TAIL, lj, ob, on, sp, len);
+        run_records(ob, on, sp, dst, src, len);
+        for (uint32_t r = lo_k + ROUND * NT_TAIL + threadIdx.x;; r += ROUND * NT_TAIL) {
+            if (__ballot(r < hi_k) == 0) break;
+            load_records(B, k, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
+            run_records(ob, on, sp, dst, src, len);
         }
         __syncthreads();
     }
-    if (bad) fail(j, ACEAPEX_E_CORRUPT);
 }
 
 // ----------------------------------------------------------------- host side
@@ -703,49 +809,19 @@ struct PhaseScope {
         i0 = g_timing.used;
         hipEvent_t e = timing_event();
         if (!e) { on = false; return; }
-        hipEventRecord(e, st);
+        (void)hipEventRecord(e, st);
     }
     ~PhaseScope()
     {
         if (!on) return;
         hipEvent_t e = timing_event();
         if (!e) return;
-        hipEventRecord(e, st);
+        (void)hipEventRecord(e, st);
         g_timing.marks.push_back({ph, i0});
     }
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-constexpr uint64_t BCUR_MAX = 1ull << 22;  // (level, block) cursors used up to this many pairs
-
-bool use_block_cursors(const aceapex_info &in)
-{
-    return (uint64_t)in.n_blocks * ((uint64_t)in.max_level + 1) <= BCUR_MAX;
-}
-
-struct WsLayout {
-    size_t status, chunks, blk_ok, rec_base, cursor, bcount, bcursor, recs, total;
-};
-
-WsLayout ws_layout(const aceapex_info &in)
-{
-    WsLayout w;
-    size_t o = 0;
-    const size_t nl = (size_t)in.max_level + 1;
-    w.status = o; o += 256;
-    w.chunks = o; o = align256(o + sizeof(ChunkDesc) * (size_t)in.n_chunks);
-    w.blk_ok = o; o = align256(o + (size_t)in.n_blocks);
-    w.rec_base = o; o = align256(o + 4 * (nl + 1));
-    w.cursor = o; o = align256(o + 4 * nl);
-    const size_t pairs = use_block_cursors(in) ? nl * (size_t)in.n_blocks : 0;
-    w.bcount = o; o = align256(o + 4 * pairs);
-    w.bcursor = o; o = align256(o + 4 * pairs);
-    w.recs = o; o = align256(o + 12ull * (size_t)in.n_seq);
-    w.total = o;
-    return w;
-}
-
 inline uint16_t rd16h(const uint8_t *p) { uint16_t v; memcpy(&v, p, 2); return v; }
 inline uint32_t rd32h(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
 inline uint64_t rd64h(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
@@ -772,6 +848,7 @@ int gpu_supported(const aceapex_info &in)
     if (in.decoded_bytes >= (1ull << 32) || in.comp_bytes >= (1ull << 32)) return ACEAPEX_E_UNSUPPORTED;
     if (in.block_log2 > BLOCK_LOG2_MAX || in.chunk_log2 > K_LOG2_MAX) return ACEAPEX_E_UNSUPPORTED;
     if ((uint64_t)in.n_seq * 3 >= (1ull << 32)) return ACEAPEX_E_UNSUPPORTED;
+    if (in.n_chunks > CHUNKS_MAX) return ACEAPEX_E_UNSUPPORTED;
     return ACEAPEX_OK;
 }
 
@@ -787,13 +864,57 @@ uint32_t level_wgs(uint64_t records)
     return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(LEVEL_WG_MAX, (records + per_wg - 1) / per_wg));
 }
 
-int launch_one(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st)
+// Level launches: one per level with records, sized to its count, and the
+// deep levels that hold few matches together in the tail workgroup.  counts
+// is null when the host does not know them (full-size launch per level).
+void launch_levels(const Batch &B, const uint64_t *counts, uint64_t n_seq, hipStream_t st)
+{
+    PhaseScope ps(PH_LEVELS, st);
+    uint32_t tail = B.max_level + 1;
+    if (counts) {
+        while (tail > 1 && counts[tail - 1] <= TAIL_LEVEL_MAX) tail--;
+        if (B.max_level + 1 - tail < 2) tail = B.max_level + 1;
+    }
+    for (uint32_t k = 0; k < tail; k++) {
+        const uint64_t cnt = counts ? counts[k] : n_seq;
+        if (counts && !cnt) continue;
+        hipLaunchKernelGGL(k_level, dim3(level_wgs(cnt)), dim3(NT), 0, st, B, k);
+    }
+    if (tail <= B.max_level) hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
+}
+
+// ---- one stream
+
+struct WsLayout {
+    size_t status, chunks, blk_ok, rec_lo, rec_hi, cursor, recs, total;
+};
+
+WsLayout ws_single(const aceapex_info &in)
+{
+    WsLayout w;
+    size_t o = 0;
+    const size_t nl = (size_t)in.max_level + 1;
+    w.status = o; o += 256;
+    w.chunks = o; o = align256(o + sizeof(ChunkDesc) * (size_t)in.n_chunks);
+    w.blk_ok = o; o = align256(o + (size_t)in.n_blocks);
+    w.rec_lo = o; o = align256(o + 4 * nl);
+    w.rec_hi = o; o = align256(o + 4 * nl);
+    w.cursor = o; o = align256(o + 4 * nl);
+    w.recs = o; o = align256(o + 12ull * (size_t)in.n_seq);
+    w.total = o;
+    return w;
+}
+
+Job make_job(const aceapex_stream &s, void *d_out, int32_t *status, ChunkDesc *chunks, uint8_t *blk_ok,
+             uint32_t c0, uint32_t b0, uint32_t lv0)
 {
     const aceapex_info &in = s.info;
-    const WsLayout w = ws_layout(in);
     Job j;
     j.comp = (const uint8_t *)s.d_comp;
     j.out = (uint8_t *)d_out;
+    j.status = status;
+    j.chunks = chunks;
+    j.blk_ok = blk_ok;
     j.n = (uint32_t)in.decoded_bytes;
     j.comp_bytes = (uint32_t)in.comp_bytes;
     j.n_blocks = in.n_blocks;
@@ -803,45 +924,186 @@ int launch_one(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_sta
     j.max_level = in.max_level;
     j.n_chunks = in.n_chunks;
     j.n_seq = in.n_seq;
-    j.chunks = (ChunkDesc *)(ws + w.chunks);
-    j.blk_ok = ws + w.blk_ok;
-    j.rec_base = (uint32_t *)(ws + w.rec_base);
-    j.cursor = (uint32_t *)(ws + w.cursor);
-    j.bcount = (uint32_t *)(ws + w.bcount);
-    j.bcursor = (uint32_t *)(ws + w.bcursor);
-    j.use_bcur = use_block_cursors(in) ? 1u : 0u;
-    j.recs = (uint32_t *)(ws + w.recs);
-    j.status = d_status ? d_status : (int32_t *)(ws + w.status);
+    j.c0 = c0;
+    j.b0 = b0;
+    j.lv0 = lv0;
+    return j;
+}
+
+int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st)
+{
+    const aceapex_info &in = s.info;
+    const WsLayout w = ws_single(in);
+    Batch B;
+    memset(&B, 0, sizeof B);
+    B.one = make_job(s, d_out, d_status ? d_status : (int32_t *)(ws + w.status), (ChunkDesc *)(ws + w.chunks),
+                     ws + w.blk_ok, 0, 0, 0);
+    B.rec_lo = (uint32_t *)(ws + w.rec_lo);
+    B.rec_hi = (uint32_t *)(ws + w.rec_hi);
+    B.cursor = (uint32_t *)(ws + w.cursor);
+    B.recs = (uint32_t *)(ws + w.recs);
+    B.n_jobs = 1;
+    B.n_blocks = in.n_blocks;
+    B.n_chunks = in.n_chunks;
+    B.max_level = in.max_level;
+    B.n_seq = in.n_seq;
     {
         PhaseScope ps(PH_SETUP, st);
-        const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(in.n_blocks, 65535));
-        hipLaunchKernelGGL(k_setup, dim3(g), dim3(NT), 0, st, j);
+        hipLaunchKernelGGL(k_setup, dim3(std::max<uint32_t>(1, std::min<uint32_t>(in.n_blocks, 65535))), dim3(NT), 0,
+                           st, B);
     }
     if (in.n_blocks) {
         {
             PhaseScope ps(PH_PARSE, st);
-            if (j.use_bcur)
-                hipLaunchKernelGGL(k_bscan, dim3(std::min<uint32_t>(in.max_level + 1, 65535)), dim3(NT), 0, st, j);
-            hipLaunchKernelGGL(k_parse, dim3(in.n_chunks), dim3(NT), 0, st, j);
+            hipLaunchKernelGGL(k_parse, dim3(in.n_chunks), dim3(NT), 0, st, B);
         }
         if (in.n_seq) {
-            PhaseScope ps(PH_LEVELS, st);
-            // with the level table on the host: one launch per level sized to it, and
-            // the deep levels that hold few matches together in the tail workgroup
-            uint32_t tail = in.max_level + 1;
-            if (s.h_levels) {
-                while (tail > 1 && s.h_levels[tail - 1] <= TAIL_LEVEL_MAX) tail--;
-                if (in.max_level + 1 - tail < 2) tail = in.max_level + 1;
-            }
-            for (uint32_t k = 0; k < tail; k++) {
-                const uint64_t cnt = s.h_levels ? s.h_levels[k] : in.n_seq;
-                if (s.h_levels && !cnt) continue;
-                hipLaunchKernelGGL(k_level, dim3(level_wgs(cnt)), dim3(NT), 0, st, j, k);
-            }
-            if (tail <= in.max_level) hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT_TAIL), 0, st, j, tail);
+            std::vector<uint64_t> cnt;
+            if (s.h_levels) cnt.assign(s.h_levels, s.h_levels + in.max_level + 1);
+            launch_levels(B, s.h_levels ? cnt.data() : nullptr, in.n_seq, st);
         }
     }
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+    return ACEAPEX_OK;
+}
+
+// ---- a batch of streams (all with host level tables), at most JOBS_MAX
+
+struct BatchLayout {
+    size_t jobs, rec_lo, rec_hi, level_lo, staged;  // staged = bytes copied from the host
+    size_t cursor, blk_job, chunk_job, chunks, blk_ok, status, recs, total;
+    uint64_t n_lv, n_blocks, n_chunks, n_seq;
+    uint32_t max_level;
+};
+
+BatchLayout ws_batch(const aceapex_desc *d, uint32_t n)
+{
+    BatchLayout w;
+    w.n_lv = w.n_blocks = w.n_chunks = w.n_seq = 0;
+    w.max_level = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        const aceapex_info &in = d[i].s.info;
+        w.n_lv += (uint64_t)in.max_level + 1;
+        w.n_blocks += in.n_blocks;
+        w.n_chunks += in.n_chunks;
+        w.n_seq += in.n_seq;
+        w.max_level = std::max(w.max_level, in.max_level);
+    }
+    size_t o = 0;
+    w.jobs = o; o = align256(o + sizeof(Job) * (size_t)n);
+    w.rec_lo = o; o = align256(o + 4 * w.n_lv);
+    w.rec_hi = o; o = align256(o + 4 * w.n_lv);
+    w.level_lo = o; o = align256(o + 4 * ((size_t)w.max_level + 2));
+    w.staged = o;
+    w.cursor = o; o = align256(o + 4 * w.n_lv);
+    w.blk_job = o; o = align256(o + 4 * w.n_blocks);
+    w.chunk_job = o; o = align256(o + 4 * w.n_chunks);
+    w.chunks = o; o = align256(o + sizeof(ChunkDesc) * w.n_chunks);
+    w.blk_ok = o; o = align256(o + w.n_blocks);
+    w.status = o; o = align256(o + 4 * (size_t)n);
+    w.recs = o; o = align256(o + 12 * w.n_seq);
+    w.total = o;
+    return w;
+}
+
+// Pinned host buffers that carry the per-batch tables to the device; a
+// buffer is reused only after the copy that last read it has run.
+struct Staging {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+thread_local Staging g_stage[4];
+thread_local unsigned g_stage_next = 0;
+
+int stage_buffer(size_t bytes, Staging *&out)
+{
+    Staging &s = g_stage[g_stage_next++ % 4];
+    hipError_t e;
+    if (s.pending && (e = hipEventSynchronize(s.ev)) != hipSuccess) return hip_fail(e);
+    s.pending = false;
+    if (!s.ev && (e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+    if (s.cap < bytes) {
+        if (s.p) (void)hipHostFree(s.p);
+        s.p = nullptr;
+        s.cap = 0;
+        if ((e = hipHostMalloc(&s.p, bytes, hipHostMallocDefault)) != hipSuccess) return hip_fail(e);
+        s.cap = bytes;
+    }
+    out = &s;
+    return ACEAPEX_OK;
+}
+
+int launch_batch(const aceapex_desc *d, uint32_t n, uint8_t *ws, hipStream_t st)
+{
+    const BatchLayout w = ws_batch(d, n);
+    Staging *sb = nullptr;
+    int rc = stage_buffer(w.staged, sb);
+    if (rc) return rc;
+    uint8_t *h = (uint8_t *)sb->p;
+    Job *hj = (Job *)(h + w.jobs);
+    uint32_t *lo = (uint32_t *)(h + w.rec_lo), *hi = (uint32_t *)(h + w.rec_hi), *llo = (uint32_t *)(h + w.level_lo);
+    // per level: matches over the batch; then each stream's slots inside its level
+    std::vector<uint64_t> tot((size_t)w.max_level + 1, 0);
+    for (uint32_t i = 0; i < n; i++)
+        for (uint32_t k = 0; k <= d[i].s.info.max_level; k++) tot[k] += d[i].s.h_levels[k];
+    std::vector<uint64_t> at((size_t)w.max_level + 1, 0);
+    uint64_t acc = 0;
+    for (uint32_t k = 0; k <= w.max_level; k++) {
+        llo[k] = (uint32_t)acc;
+        at[k] = acc;
+        acc += tot[k];
+    }
+    llo[w.max_level + 1] = (uint32_t)acc;
+    uint64_t c0 = 0, b0 = 0, lv0 = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        const aceapex_info &in = d[i].s.info;
+        int32_t *status = d[i].d_status ? d[i].d_status : (int32_t *)(ws + w.status) + i;
+        hj[i] = make_job(d[i].s, d[i].d_out, status, (ChunkDesc *)(ws + w.chunks) + c0, ws + w.blk_ok + b0,
+                         (uint32_t)c0, (uint32_t)b0, (uint32_t)lv0);
+        for (uint32_t k = 0; k <= in.max_level; k++) {
+            lo[lv0 + k] = (uint32_t)at[k];
+            at[k] += d[i].s.h_levels[k];
+            hi[lv0 + k] = (uint32_t)at[k];
+        }
+        c0 += in.n_chunks;
+        b0 += in.n_blocks;
+        lv0 += (uint64_t)in.max_level + 1;
+    }
+    hipError_t e = hipMemcpyAsync(ws, h, w.staged, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((e = hipEventRecord(sb->ev, st)) != hipSuccess) return hip_fail(e);
+    sb->pending = true;
+
+    Batch B;
+    memset(&B, 0, sizeof B);
+    B.jobs = (const Job *)(ws + w.jobs);
+    B.blk_job = (uint32_t *)(ws + w.blk_job);
+    B.chunk_job = (uint32_t *)(ws + w.chunk_job);
+    B.rec_lo = (uint32_t *)(ws + w.rec_lo);
+    B.rec_hi = (uint32_t *)(ws + w.rec_hi);
+    B.cursor = (uint32_t *)(ws + w.cursor);
+    B.level_lo = (const uint32_t *)(ws + w.level_lo);
+    B.recs = (uint32_t *)(ws + w.recs);
+    B.n_jobs = n;
+    B.n_blocks = (uint32_t)w.n_blocks;
+    B.n_chunks = (uint32_t)w.n_chunks;
+    B.max_level = w.max_level;
+    B.n_seq = (uint32_t)w.n_seq;
+    {
+        PhaseScope ps(PH_SETUP, st);
+        hipLaunchKernelGGL(k_map, dim3(n), dim3(NT), 0, st, B);
+        const uint64_t g = std::max<uint64_t>(std::max<uint64_t>(1, n), std::min<uint64_t>(w.n_blocks, 65535));
+        hipLaunchKernelGGL(k_setup, dim3((uint32_t)g), dim3(NT), 0, st, B);
+    }
+    if (w.n_chunks) {
+        PhaseScope ps(PH_PARSE, st);
+        hipLaunchKernelGGL(k_parse, dim3((uint32_t)w.n_chunks), dim3(NT), 0, st, B);
+    }
+    if (w.n_seq) launch_levels(B, tot.data(), w.n_seq, st);
+    e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e);
     return ACEAPEX_OK;
 }
@@ -856,6 +1118,39 @@ int check_stream_args(const aceapex_stream *s, const void *d_out, uint64_t cap)
     if (s->info.decoded_bytes && !d_out) return ACEAPEX_E_INVAL;
     if (cap < s->info.decoded_bytes) return ACEAPEX_E_CAPACITY;
     return ACEAPEX_OK;
+}
+
+// Streams d[0, m) that one launch sequence takes, m >= 1: at most JOBS_MAX
+// streams, and batch-wide record, chunk, block and level counts that keep
+// every 32-bit index of the batch layout (and the k_parse grid) in range.
+uint32_t group_size(const aceapex_desc *d, uint32_t n)
+{
+    uint64_t seq = 0, chunks = 0, blocks = 0, levels = 0;
+    uint32_t m = 0;
+    while (m < n && m < JOBS_MAX) {
+        const aceapex_info &in = d[m].s.info;
+        seq += in.n_seq;
+        chunks += in.n_chunks;
+        blocks += in.n_blocks;
+        levels += (uint64_t)in.max_level + 1;
+        if (m && (seq * 3 >= (1ull << 32) || chunks > CHUNKS_MAX || blocks >= (1ull << 31) || levels >= (1ull << 31)))
+            break;
+        m++;
+    }
+    return m;
+}
+
+// Workspace of decode_many: the batched layout per group of streams, or one
+// single-stream layout per stream, whichever is larger.
+size_t many_bytes(const aceapex_desc *d, uint32_t n)
+{
+    size_t batched = 0, single = 0;
+    for (uint32_t i = 0, m; i < n; i += m) {
+        m = group_size(d + i, n - i);
+        batched += ws_batch(d + i, m).total;
+    }
+    for (uint32_t i = 0; i < n; i++) single += ws_single(d[i].s.info).total;
+    return std::max(batched, single);
 }
 
 }  // namespace
@@ -905,12 +1200,9 @@ int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *cou
 size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n)
 {
     if (!h_descs) return 0;
-    size_t tot = 0;
-    for (uint32_t i = 0; i < n; i++) {
+    for (uint32_t i = 0; i < n; i++)
         if (!info_consistent(h_descs[i].s.info)) return 0;
-        tot += ws_layout(h_descs[i].s.info).total;
-    }
-    return tot;
+    return many_bytes(h_descs, n);
 }
 
 int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, void *d_workspace,
@@ -918,28 +1210,38 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
 {
     int rc = check_stream_args(stream, d_out, out_capacity);
     if (rc) return rc;
-    const size_t need = ws_layout(stream->info).total;
+    const size_t need = ws_single(stream->info).total;
     if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need) return ACEAPEX_E_WORKSPACE;
-    return launch_one(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream);
+    return launch_single(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream);
 }
 
 int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace, size_t ws_bytes,
                         void *hip_stream)
 {
     if (!h_descs && n) return ACEAPEX_E_INVAL;
-    size_t need = 0;
+    bool tables = true;
     for (uint32_t i = 0; i < n; i++) {
         int rc = check_stream_args(&h_descs[i].s, h_descs[i].d_out, h_descs[i].out_capacity);
         if (rc) return rc;
-        need += ws_layout(h_descs[i].s.info).total;
+        tables = tables && h_descs[i].s.h_levels;
     }
-    if (n && (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need)) return ACEAPEX_E_WORKSPACE;
-    size_t off = 0;
-    for (uint32_t i = 0; i < n; i++) {
-        int rc = launch_one(h_descs[i].s, h_descs[i].d_out, (uint8_t *)d_workspace + off, h_descs[i].d_status,
-                            (hipStream_t)hip_stream);
+    if (n && (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < many_bytes(h_descs, n)))
+        return ACEAPEX_E_WORKSPACE;
+    uint8_t *ws = (uint8_t *)d_workspace;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!tables) {  // without the host level tables: one stream after the other
+        for (uint32_t i = 0; i < n; i++) {
+            int rc = launch_single(h_descs[i].s, h_descs[i].d_out, ws, h_descs[i].d_status, st);
+            if (rc) return rc;
+            ws += ws_single(h_descs[i].s.info).total;
+        }
+        return ACEAPEX_OK;
+    }
+    for (uint32_t i = 0, m; i < n; i += m) {
+        m = group_size(h_descs + i, n - i);
+        int rc = launch_batch(h_descs + i, m, ws, st);
         if (rc) return rc;
-        off += ws_layout(h_descs[i].s.info).total;
+        ws += ws_batch(h_descs + i, m).total;
     }
     return ACEAPEX_OK;
 }

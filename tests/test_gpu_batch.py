@@ -1,0 +1,131 @@
+"""GPU parity of the batched decode (aceapex_decode_many): many independent
+streams in one launch sequence must each decode exactly as alone, including
+when some streams of the batch are corrupt."""
+import numpy as np
+import pytest
+
+import oracle
+import streamgen
+import synth
+from gpu_util import GUARD, POISON, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def mixed_streams(count, seed):
+    """(original bytes, stream) pairs of varied kind, size, block size and options."""
+    rng = np.random.default_rng(seed)
+    out = []
+    kinds = ["markov", "fastq", "random", "wiki"]
+    for i in range(count):
+        kind = kinds[i % 4]
+        n = int(np.exp(rng.uniform(np.log(200), np.log(600_000))))
+        x = synth.make(kind, n, seed * 1000 + i)
+        opts = dict(block_log2=int(rng.choice([12, 16, 20])), flatten=int(rng.integers(0, 3)),
+                    max_depth=int(rng.choice([0, 0, 2, 8])), chunk_log2=int(rng.choice([4, 8, 10])))
+        out.append((x, oracle.encode(x, **opts)))
+    out.append((np.zeros(0, np.uint8), oracle.encode(b"")))
+    u = np.random.default_rng(7).permutation(256)[:16].astype(np.uint8).tobytes()
+    dbl = u * 4096
+    out.append((np.frombuffer(dbl, np.uint8), oracle.encode(dbl, hash_bits=12)))
+    m = 600
+    blocks = [([(4, 4, 0)] + [(0, 4, 4 * i) for i in range(1, m)], 0)]
+    s, want = streamgen.build(blocks, b"abcd", 4 + 4 * m, block_log2=14, chunk_log2=5)
+    out.append((np.frombuffer(want, np.uint8), s))
+    return out
+
+
+def run_batch(pairs, with_tables=True):
+    import torch
+
+    import paper_2606_04268_amd as ax
+
+    dss = [ax.to_device(s) for _, s in pairs]
+    if not with_tables:
+        for d in dss:
+            d.levels = None
+    bufs, outs = [], []
+    for d in dss:
+        b = torch.full((d.n + 2 * GUARD,), POISON, dtype=torch.uint8, device="cuda")
+        bufs.append(b)
+        outs.append(b[GUARD:GUARD + max(d.n, 16)])
+    statuses = torch.full((len(dss),), 12345, dtype=torch.int32, device="cuda")
+    ax.decode_many(dss, outs=outs, statuses=statuses)
+    torch.cuda.synchronize()
+    st = statuses.cpu().numpy()
+    res = []
+    for d, b in zip(dss, bufs):
+        h = b.cpu().numpy()
+        assert (h[:GUARD] == POISON).all(), "write below an output buffer"
+        assert (h[GUARD + d.n:] == POISON).all(), "write above an output buffer"
+        res.append(h[GUARD:GUARD + d.n])
+    return res, st
+
+
+@pytest.mark.parametrize("with_tables", [True, False], ids=["batched", "one_by_one"])
+def test_batch_of_mixed_streams(with_tables):
+    pairs = mixed_streams(24, 3)
+    say(f"[gpu] decode_many {len(pairs)} streams with_tables={with_tables}")
+    res, st = run_batch(pairs, with_tables)
+    assert (st == 0).all(), st
+    for (x, _), got in zip(pairs, res):
+        assert np.array_equal(got, x)
+
+
+def test_large_batch_many_small_streams():
+    """Hundreds of 4 KB .. 64 KB streams in one call."""
+    rng = np.random.default_rng(11)
+    pairs = []
+    for i in range(300):
+        n = int(rng.integers(4096, 65536))
+        x = synth.make(["markov", "fastq", "random"][i % 3], n, 5000 + i)
+        pairs.append((x, oracle.encode(x, block_log2=16, flatten=i % 2)))
+    say("[gpu] decode_many 300 small streams")
+    res, st = run_batch(pairs)
+    assert (st == 0).all()
+    for (x, _), got in zip(pairs, res):
+        assert np.array_equal(got, x)
+
+
+def _corrupt(s, rng):
+    """A copy of stream s with a few bytes flipped past the header (the header
+    stays valid so that the host accepts it)."""
+    bad = s.copy()
+    h = oracle.header_fields(s)
+    start = 64 + 16 * (h["n_blocks"] + 1) + (4 * (h["max_level"] + 1) + 15) // 16 * 16
+    for _ in range(int(rng.integers(1, 6))):
+        i = int(rng.integers(start, s.size))
+        bad[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+    return bad
+
+
+def test_corrupt_streams_do_not_disturb_their_batch():
+    """Valid streams decode exactly and no output buffer is overrun, whatever
+    the corrupt streams beside them contain."""
+    rng = np.random.default_rng(2024)
+    good = mixed_streams(10, 9)
+    for trial in range(4):
+        pairs = []
+        corrupt_at = set()
+        for i, (x, s) in enumerate(good):
+            if i % 3 == trial % 3 and x.size > 1000:
+                pairs.append((x, _corrupt(s, rng)))
+                corrupt_at.add(i)
+            else:
+                pairs.append((x, s))
+        say(f"[gpu] corrupt batch trial {trial}: corrupt streams {sorted(corrupt_at)}")
+        res, st = run_batch(pairs)
+        for i, ((x, _), got) in enumerate(zip(pairs, res)):
+            if i in corrupt_at:
+                assert st[i] in (0, -3)
+            else:
+                assert st[i] == 0
+                assert np.array_equal(got, x)
