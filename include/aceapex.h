@@ -175,6 +175,71 @@ int aceapex_timing(int enable);
  * ACEAPEX_E_INVAL or ACEAPEX_E_HIP. */
 int aceapex_timing_read(float *ms, uint32_t *count, uint32_t n);
 
+/* ---------------------------------------------------- plans (batched mode) */
+
+/* A plan lays a batch out once and launches it many times (Sec. 7.5: the
+ * streams of a batch are independent).  aceapex_plan_create checks the
+ * descriptors as aceapex_decode_many does -- every descriptor must carry
+ * h_levels -- and writes the batch's host-side tables into the workspace
+ * (synchronously, on hip_stream); the level counts are copied, so h_levels
+ * need not outlive the call.  A launch then only enqueues kernels: no
+ * host-to-device copy, no allocation and no memset, so aceapex_plan_launch
+ * may be captured into the caller's HIP graph, and aceapex_plan_launch_graph
+ * captures the sequence once into a graph of its own and replays it.
+ *
+ * Ownership: the plan is host memory of the library until
+ * aceapex_plan_destroy.  The compressed inputs, outputs, status words and
+ * the workspace stay the caller's; they must stay allocated, and the
+ * workspace untouched by anything else, while the plan lives.  Launches of
+ * one plan must not overlap (they share the workspace), and run on the
+ * device that was current at creation.  Each launch decodes every stream
+ * again and rewrites each status word. */
+typedef struct aceapex_plan aceapex_plan;
+
+/* Schedule of the level phase (Sec. 7.1 wavefront).  Any values in range give
+ * the same bytes; they only change the speed. */
+typedef struct {
+    uint32_t level_wg_max;   /* workgroups of one level launch, at most (1..65535; default 2048)    */
+    uint32_t tail_level_max; /* the deepest levels, while each holds at most this many matches, run  */
+                             /* together in one workgroup (default 8192; 0 = one launch per level)   */
+    uint32_t long_copy;      /* matches longer than this are copied by a whole wave (16..2^21; 128)  */
+    uint32_t xcd_parts;      /* contiguous parts of a level's matches, one per XCD (1..8; default 8) */
+} aceapex_tuning;
+
+/* The default schedule (the one aceapex_decode and aceapex_decode_many use). */
+void aceapex_tuning_defaults(aceapex_tuning *t);
+
+/* Create a plan for h_descs[0, n) with workspace d_workspace (at least
+ * aceapex_workspace_bytes(h_descs, n), 256-byte aligned).  tuning may be NULL
+ * (defaults).  Returns ACEAPEX_OK, ACEAPEX_E_INVAL (null plan, a descriptor
+ * without h_levels, a tuning value out of range), the argument errors of
+ * aceapex_decode_many, ACEAPEX_E_NOMEM or ACEAPEX_E_HIP. */
+int aceapex_plan_create(const aceapex_desc *h_descs, uint32_t n, void *d_workspace, size_t ws_bytes,
+                        const aceapex_tuning *tuning, void *hip_stream, aceapex_plan **plan);
+
+/* Enqueue one decode of every stream of the plan on hip_stream (kernel
+ * launches only).  Returns ACEAPEX_OK, ACEAPEX_E_INVAL or ACEAPEX_E_HIP. */
+int aceapex_plan_launch(aceapex_plan *plan, void *hip_stream);
+
+/* As aceapex_plan_launch, through a HIP graph captured (on a private stream
+ * of default priority) at the first call after creation or a tuning change. */
+int aceapex_plan_launch_graph(aceapex_plan *plan, void *hip_stream);
+
+/* Replace / read the plan's schedule (a change drops the captured graph). */
+int aceapex_plan_set_tuning(aceapex_plan *plan, const aceapex_tuning *tuning);
+int aceapex_plan_get_tuning(const aceapex_plan *plan, aceapex_tuning *tuning);
+
+/* Autotune the schedule on this plan's own streams: coordinate descent over
+ * level_wg_max, tail_level_max, long_copy and xcd_parts, each candidate timed
+ * with HIP events over reps launches after one warm-up; a candidate is kept
+ * when it is at least 1% faster.  The plan keeps the winner, also written to
+ * *best when best is not NULL.  Synchronous; runs about 15 * (reps + 1)
+ * decodes of the batch, each leaving the outputs decoded. */
+int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceapex_tuning *best);
+
+/* Free the plan (NULL is ignored).  Call it once no launch is in flight. */
+void aceapex_plan_destroy(aceapex_plan *plan);
+
 /* ------------------------------------------------------------ host encoder */
 
 /* Encoder parameters.  The parse is greedy over hash chains of 4-byte

@@ -14,7 +14,7 @@ from . import _abi
 from ._abi import AceapexError, Info
 
 __all__ = ["AceapexError", "Info", "DeviceStream", "probe", "encode", "to_device",
-           "workspace_bytes", "decode", "decode_many", "check_status", "content_hash"]
+           "workspace_bytes", "decode", "decode_many", "check_status", "content_hash", "Plan"]
 
 
 def _torch():
@@ -138,3 +138,104 @@ def check_status(status) -> None:
     bad = np.nonzero(vals)[0]
     if bad.size:
         raise AceapexError(int(vals[bad[0]]), f"device status of stream {int(bad[0])}")
+
+
+class Plan:
+    """A batch of device streams laid out once in its workspace
+    (aceapex_plan_create); every launch decodes all of them again by
+    enqueueing kernels only, directly or through a captured HIP graph.
+
+    The tensors given (or allocated here) are kept referenced for the plan's
+    lifetime, as the C ABI requires."""
+
+    def __init__(self, streams, outs=None, statuses=None, workspace=None, stream=None, tuning=None):
+        torch = _torch()
+        self.streams = list(streams)
+        dev = self.streams[0].comp.device if self.streams else "cuda"
+        if outs is None:
+            outs = [torch.empty(max(s.n, 1), dtype=torch.uint8, device=dev) for s in self.streams]
+        if statuses is None:
+            statuses = torch.zeros(max(len(self.streams), 1), dtype=torch.int32, device=dev)
+        self.outs, self.statuses = list(outs), statuses
+        descs = [_abi.Desc(s.abi(), o.data_ptr(), o.numel(), statuses.data_ptr() + 4 * i)
+                 for i, (s, o) in enumerate(zip(self.streams, self.outs))]
+        need = _abi.workspace_bytes(descs) if descs else 0
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        self.workspace = workspace
+        t = None
+        if tuning is not None:
+            t = _abi.tuning_defaults()
+            for k, v in dict(tuning).items():
+                setattr(t, k, int(v))
+        self._h = _abi.plan_create(descs, workspace.data_ptr(), workspace.numel(), t, _stream_handle(stream))
+
+    def launch(self, stream=None, graph: bool = False):
+        """Enqueue one decode of every stream (asynchronous)."""
+        rc = _abi.plan_launch(self._handle(), _stream_handle(stream), graph)
+        if rc:
+            raise AceapexError(rc, "plan_launch")
+
+    @property
+    def tuning(self) -> dict:
+        return _abi.plan_get_tuning(self._handle()).as_dict()
+
+    def set_tuning(self, **knobs):
+        t = _abi.plan_get_tuning(self._handle())
+        for k, v in knobs.items():
+            if not hasattr(t, k):
+                raise TypeError(f"unknown tuning knob {k}")
+            setattr(t, k, int(v))
+        rc = _abi.plan_set_tuning(self._handle(), t)
+        if rc:
+            raise AceapexError(rc, "plan_set_tuning")
+
+    def signature(self) -> str:
+        """Key of this batch's shape for a tuning cache: stream count and the
+        rounded logs of its decoded bytes and matches, and its deepest level."""
+        import math
+
+        n = sum(s.n for s in self.streams)
+        m = sum(int(s.info.n_seq) for s in self.streams)
+        lv = max((int(s.info.max_level) for s in self.streams), default=0)
+        return f"s{len(self.streams)}-b{round(math.log2(n + 1))}-m{round(math.log2(m + 1))}-l{lv}"
+
+    def tune(self, reps: int = 3, stream=None, cache: str | None = None) -> dict:
+        """Autotune the level schedule (aceapex_plan_tune) and return it.  With
+        a cache file (JSON), a schedule stored for the same signature is reused
+        instead, and a new one is stored."""
+        import json
+        import os
+
+        key = self.signature()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tuning(**table[key])
+                return dict(table[key])
+        best = _abi.plan_tune(self._handle(), _stream_handle(stream), reps).as_dict()
+        if cache:
+            table[key] = best
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return best
+
+    def _handle(self):
+        if not self._h:
+            raise AceapexError(_abi.E_INVAL, "plan already closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _abi.plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

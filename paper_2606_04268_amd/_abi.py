@@ -50,6 +50,14 @@ class EncOpts(ctypes.Structure):
         "tiebreak", "chunk_log2", "threads")]
 
 
+class Tuning(ctypes.Structure):
+    """aceapex_tuning."""
+    _fields_ = [(n, ctypes.c_uint32) for n in ("level_wg_max", "tail_level_max", "long_copy", "xcd_parts")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class AceapexError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         msg = strerror(code) if _lib is not None else str(code)
@@ -59,7 +67,9 @@ class AceapexError(RuntimeError):
 
 EXPORTS = ("aceapex_probe", "aceapex_level_table", "aceapex_workspace_bytes", "aceapex_decode", "aceapex_decode_many",
            "aceapex_strerror", "aceapex_last_hip_error", "aceapex_enc_defaults", "aceapex_encode",
-           "aceapex_free", "aceapex_timing", "aceapex_timing_read")
+           "aceapex_free", "aceapex_timing", "aceapex_timing_read", "aceapex_tuning_defaults",
+           "aceapex_plan_create", "aceapex_plan_launch", "aceapex_plan_launch_graph", "aceapex_plan_set_tuning",
+           "aceapex_plan_get_tuning", "aceapex_plan_tune", "aceapex_plan_destroy")
 
 PHASES = ("setup", "parse", "levels")
 
@@ -104,6 +114,22 @@ def load():
     lib.aceapex_timing_read.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint32),
                                         ctypes.c_uint32]
     lib.aceapex_timing_read.restype = ctypes.c_int
+    lib.aceapex_tuning_defaults.argtypes = [ctypes.POINTER(Tuning)]
+    lib.aceapex_tuning_defaults.restype = None
+    lib.aceapex_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint32, vp, ctypes.c_size_t,
+                                        ctypes.POINTER(Tuning), vp, ctypes.POINTER(vp)]
+    lib.aceapex_plan_create.restype = ctypes.c_int
+    for name in ("aceapex_plan_launch", "aceapex_plan_launch_graph"):
+        getattr(lib, name).argtypes = [vp, vp]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.aceapex_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.aceapex_plan_set_tuning.restype = ctypes.c_int
+    lib.aceapex_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.aceapex_plan_get_tuning.restype = ctypes.c_int
+    lib.aceapex_plan_tune.argtypes = [vp, vp, ctypes.c_uint32, ctypes.POINTER(Tuning)]
+    lib.aceapex_plan_tune.restype = ctypes.c_int
+    lib.aceapex_plan_destroy.argtypes = [vp]
+    lib.aceapex_plan_destroy.restype = None
     _lib = lib
     return lib
 
@@ -189,3 +215,50 @@ def timing_read():
     if rc:
         raise AceapexError(rc, "timing_read")
     return {PHASES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def tuning_defaults() -> Tuning:
+    t = Tuning()
+    load().aceapex_tuning_defaults(ctypes.byref(t))
+    return t
+
+
+def plan_create(descs, d_ws: int, ws_bytes: int, tuning, hip_stream: int) -> int:
+    """aceapex_plan_create; returns the plan handle (an integer)."""
+    arr = (Desc * len(descs))(*descs)
+    h = ctypes.c_void_p()
+    rc = load().aceapex_plan_create(arr, len(descs), d_ws, ws_bytes,
+                                    ctypes.byref(tuning) if tuning is not None else None, hip_stream,
+                                    ctypes.byref(h))
+    if rc:
+        raise AceapexError(rc, "plan_create")
+    return h.value
+
+
+def plan_launch(plan: int, hip_stream: int, graph: bool = False) -> int:
+    f = load().aceapex_plan_launch_graph if graph else load().aceapex_plan_launch
+    return f(plan, hip_stream)
+
+
+def plan_set_tuning(plan: int, tuning: Tuning) -> int:
+    return load().aceapex_plan_set_tuning(plan, ctypes.byref(tuning))
+
+
+def plan_get_tuning(plan: int) -> Tuning:
+    t = Tuning()
+    rc = load().aceapex_plan_get_tuning(plan, ctypes.byref(t))
+    if rc:
+        raise AceapexError(rc, "plan_get_tuning")
+    return t
+
+
+def plan_tune(plan: int, hip_stream: int, reps: int) -> Tuning:
+    t = Tuning()
+    rc = load().aceapex_plan_tune(plan, hip_stream, reps, ctypes.byref(t))
+    if rc:
+        raise AceapexError(rc, "plan_tune")
+    return t
+
+
+def plan_destroy(plan: int) -> None:
+    load().aceapex_plan_destroy(plan)

@@ -57,9 +57,11 @@ constexpr uint32_t LEN_BITS = 21;           // a match length needs 21 bits (blo
 constexpr uint32_t LEN_MASK = (1u << LEN_BITS) - 1;
 constexpr uint32_t JOBS_MAX = 1u << (32 - LEN_BITS);  // streams per launch sequence
 constexpr uint32_t ROUND = 4;               // records per thread per round of k_level / k_tail
+// Default schedule (each value can be changed per plan, see aceapex_tuning):
 constexpr uint32_t LONG_COPY = 128;         // matches longer than this are copied by a whole wave
 constexpr uint32_t LEVEL_WG_MAX = 2048;     // workgroups of one level launch, at most
 constexpr uint32_t TAIL_LEVEL_MAX = 8192;   // levels with at most this many matches may join the tail
+constexpr uint32_t XCD_PARTS = 8;           // contiguous parts of a level's records, one per XCD
 constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
 constexpr uint64_t CHUNKS_MAX = 1ull << 24;  // chunks of one launch sequence (the k_parse grid), at most
 
@@ -105,6 +107,8 @@ struct Batch {
     uint32_t *recs;             // 3 u32 per match: dst, src, len | stream << LEN_BITS
     uint32_t n_jobs, n_blocks, n_chunks, max_level;  // totals over the batch, highest level
     uint32_t n_seq;             // matches over the batch
+    uint32_t long_copy;         // matches longer than this are copied by a whole wave
+    uint32_t xcd_parts;         // k_level: contiguous parts of a level's records (1..8)
 };
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
@@ -168,10 +172,11 @@ __device__ __forceinline__ void wave_copy(uint8_t *d, const uint8_t *s, uint32_t
 // stream's output ob[u] of on[u] bytes.  Matches of at most 16 bytes take one
 // 16-byte load of their source (when 16 bytes are there to read: bytes past
 // the match are read and discarded) and exact stores; all loads of the round
-// are issued before the stores.  Longer matches are then copied by the whole
-// wave, one at a time.
+// are issued before the stores.  Matches up to long_copy bytes are copied by
+// their own lane; longer ones are then copied by the whole wave, one at a time.
 __device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *on, int32_t *const *sp,
-                                            const uint32_t *dst, const uint32_t *src, uint32_t *len)
+                                            const uint32_t *dst, const uint32_t *src, uint32_t *len,
+                                            uint32_t long_copy)
 {
     uint64_t lo[ROUND], hi[ROUND];
 #pragma unroll
@@ -193,13 +198,13 @@ __device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *
         if (!len[u]) continue;
         if (len[u] <= 16 && (uint64_t)src[u] + 16 <= on[u]) {
             store_upto16(ob[u] + dst[u], lo[u], hi[u], len[u]);
-        } else if (len[u] <= LONG_COPY) {
+        } else if (len[u] <= long_copy) {
             copy_bytes(ob[u] + dst[u], ob[u] + src[u], len[u]);
         }
     }
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
-        uint64_t m = __ballot(len[u] > LONG_COPY);
+        uint64_t m = __ballot(len[u] > long_copy);
         while (m) {
             const int lane = __ffsll((unsigned long long)m) - 1;
             m &= m - 1;
@@ -335,32 +340,39 @@ __device__ uint64_t wg_excl_scan64(uint64_t v, uint64_t *tmp, uint64_t &total)
 // holds exactly cnt well-formed values.
 __device__ bool wave_varints(const uint8_t *p, uint32_t nb, uint32_t cnt, uint32_t *vals)
 {
+    constexpr uint32_t WINDOWS = (4 * (K_MAX + 1) + 255) / 256;  // the longest slice a chunk may hold
     const uint32_t lane = threadIdx.x & 63;
+    // every window's dword is loaded before any is decoded
+    uint32_t v[WINDOWS];
+#pragma unroll
+    for (uint32_t i = 0; i < WINDOWS; i++) {
+        const uint32_t o = 256 * i + 4 * lane;
+        if (o + 4 <= nb) {
+            v[i] = ld32(p + o);
+        } else {
+            v[i] = 0x80808080u;  // bytes past the slice: continuation, never a value end
+            for (uint32_t k = 0; k < 4; k++)
+                if (o + k < nb) v[i] = (v[i] & ~(0xffu << (8 * k))) | ((uint32_t)p[o + k] << (8 * k));
+        }
+    }
     uint32_t prev_last = 0;  // dword left of the window; zero bytes end any backward walk
     uint32_t base = 0;
-    bool ok = true;
-    for (uint32_t w = 0; w < nb; w += 256) {
-        const uint32_t o = w + 4 * lane;
-        uint32_t v;
-        if (o + 4 <= nb) {
-            v = ld32(p + o);
-        } else {
-            v = 0x80808080u;  // bytes past the slice: continuation, never a value end
-            for (uint32_t k = 0; k < 4; k++)
-                if (o + k < nb) v = (v & ~(0xffu << (8 * k))) | ((uint32_t)p[o + k] << (8 * k));
-        }
-        const uint32_t term = ~v & 0x80808080u;
+    bool ok = nb <= 256 * WINDOWS;
+#pragma unroll
+    for (uint32_t i = 0; i < WINDOWS; i++) {
+        if (256 * i >= nb) continue;  // (uniform) past the slice
+        const uint32_t term = ~v[i] & 0x80808080u;
         const uint32_t c = __popc(term);
         const uint32_t incl = wave_incl_scan32(c);
         const uint32_t tot = __shfl(incl, 63, 64);
-        uint32_t pv = __shfl_up(v, 1, 64);
+        uint32_t pv = __shfl_up(v[i], 1, 64);
         if (lane == 0) pv = prev_last;
-        const uint64_t win = ((uint64_t)v << 32) | pv;
+        const uint64_t win = ((uint64_t)v[i] << 32) | pv;
         uint32_t idx = base + incl - c;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             if (!(term & (0x80u << (8 * k)))) continue;
-            uint32_t val = (v >> (8 * k)) & 0x7f;
+            uint32_t val = (v[i] >> (8 * k)) & 0x7f;
             int q = 3 + k, n = 0;
             for (; n < 4; n++, q--) {
                 const uint32_t byte = (uint32_t)(win >> (8 * q)) & 0xff;
@@ -372,7 +384,7 @@ __device__ bool wave_varints(const uint8_t *p, uint32_t nb, uint32_t cnt, uint32
             idx++;
         }
         base += tot;
-        prev_last = __shfl(v, 63, 64);
+        prev_last = __shfl(v[i], 63, 64);
     }
     ok = ok && base == cnt && (nb == 0 || p[nb - 1] < 0x80);
     return __ballot(!ok) == 0;
@@ -537,7 +549,7 @@ struct ParseLds {
     uint32_t bad;
 } __attribute__((aligned(16)));
 
-__global__ void __launch_bounds__(NT) k_parse(Batch B)
+__global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
 {
     __shared__ ParseLds L;
     const uint32_t t = threadIdx.x, wave = t >> 6;
@@ -567,9 +579,15 @@ __global__ void __launch_bounds__(NT) k_parse(Batch B)
     const uint32_t ncmd = ns + (d.nseq_last >> 31);
     const bool one_byte = d.cmd_n == ncmd && d.len_n == ns && d.lvl_n == ns;
     const uint32_t e0 = t * PER;
+    // a full chunk (NT * PER sequences) that also holds its block's trailing
+    // run: that run is the command past every thread's range.  Every thread
+    // reads it (it ends the chunk's span and its literals); the last thread
+    // adds it to the scan, and the workgroup copies it after the other runs.
+    const bool tail_cmd = ncmd > NT * PER;
 
     // this thread's sequences e0 .. e0+3: run, match length and level
     uint32_t r[PER], m[PER], l[PER], src[PER];
+    uint32_t rt = 0;  // the trailing run when tail_cmd (uniform)
     bool bad = false;
     {
         const u128u o4 = e0 + PER <= ns ? *(const u128u *)(j.comp + d.off_at + 4 * e0) : u128u{0, 0, 0, 0};
@@ -582,6 +600,10 @@ __global__ void __launch_bounds__(NT) k_parse(Batch B)
         const uint32_t lw = bytes4(j.comp + d.len_at, e0, ns);
         const uint32_t vw = bytes4(j.comp + d.lvl_at, e0, ns);
         if ((cw | lw | vw) & 0x80808080u) bad = true;  // a continuation byte where every value is one byte
+        if (tail_cmd) {
+            rt = j.comp[d.cmd_at + NT * PER];
+            if (rt & 0x80u) bad = true;
+        }
 #pragma unroll
         for (uint32_t u = 0; u < PER; u++) {
             r[u] = (cw >> (8 * u)) & 0xff;
@@ -606,6 +628,7 @@ __global__ void __launch_bounds__(NT) k_parse(Batch B)
             m[u] = e < ns ? L.u.v.mlen[e] + j.min_match : 0;
             l[u] = e < ns ? L.u.v.lvl[e] : 0;
         }
+        if (tail_cmd) rt = L.u.v.run[NT * PER];
     }
 
     // output and literal offsets: workgroup scan over (run + match, run)
@@ -615,6 +638,9 @@ __global__ void __launch_bounds__(NT) k_parse(Batch B)
         if (r[u] > d.out_len || m[u] > d.out_len || (e0 + u < ns && l[u] > j.max_level)) bad = true;
         acc += ((uint64_t)(r[u] + m[u]) << 32) | r[u];
     }
+    rt = __builtin_amdgcn_readfirstlane(rt);
+    if (rt > d.out_len) bad = true;
+    if (t == NT - 1) acc += ((uint64_t)rt << 32) | rt;
     uint64_t tot;
     const uint64_t ex = wg_excl_scan64(bad ? 0 : acc, L.tmp, tot);
     if (bad) L.bad = 1;
@@ -633,9 +659,35 @@ __global__ void __launch_bounds__(NT) k_parse(Batch B)
     const bool tiled = span_end - base16 <= TILE_BYTES;
     uint32_t pos = d.out_base + (uint32_t)(ex >> 32), lq = (uint32_t)ex;
     uint32_t dst[PER], rank[PER];
+    // With matches of at least 3 bytes between runs, no 4-byte word of the
+    // output holds literal bytes of two runs.  A run is then placed as the
+    // whole aligned words that cover it (aligned LDS stores, no partial ones);
+    // their other bytes lie in the neighbouring matches, which the level
+    // launches rewrite.
+    const bool words = tiled && j.min_match >= 3;
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
-        if (r[u]) {
+        if (r[u] && words) {
+            const uint32_t a0 = pos - base16, w0 = a0 & ~3u, w1 = (a0 + r[u] + 3) & ~3u;
+            const uint64_t s0 = (uint64_t)d.lit_at + lq - (a0 - w0);  // stream byte that lands on tile byte w0
+            for (uint32_t o = w0; o < w1; o += 16) {
+                const uint64_t sa = s0 + (o - w0);
+                u128u v;
+                if (sa + 16 <= j.comp_bytes) {
+                    v = *(const u128u *)(j.comp + sa);
+                } else {
+                    uint32_t x[4] = {0, 0, 0, 0};
+                    for (uint32_t k = 0; k < 16 && sa + k < j.comp_bytes; k++) x[k >> 2] |= (uint32_t)j.comp[sa + k] << (8 * (k & 3));
+                    v = u128u{x[0], x[1], x[2], x[3]};
+                }
+                uint32_t *tw = (uint32_t *)(L.u.tile + o);
+                const uint32_t nw = min(4u, (w1 - o) >> 2);
+                tw[0] = v.a;
+                if (nw > 1) tw[1] = v.b;
+                if (nw > 2) tw[2] = v.c;
+                if (nw > 3) tw[3] = v.d;
+            }
+        } else if (r[u]) {
             const uint8_t *ls = j.comp + d.lit_at + lq;
             if (!tiled) {
                 copy_bytes(j.out + pos, ls, r[u]);
@@ -656,6 +708,21 @@ __global__ void __launch_bounds__(NT) k_parse(Batch B)
         lq += r[u];
         dst[u] = pos;
         pos += m[u];
+    }
+    if (rt) {  // the trailing run of a full chunk, copied by the whole workgroup
+        const uint32_t at = d.out_base + d.out_len - rt;
+        const uint8_t *ls = j.comp + d.lit_at + (d.lit_n - rt);
+        for (uint32_t o = 16 * t; o < rt; o += 16 * NT) {
+            const uint32_t n = min(16u, rt - o);
+            if (!tiled) {
+                copy_bytes(j.out + at + o, ls + o, n);
+            } else if ((uint64_t)d.lit_at + (d.lit_n - rt) + o + 16 <= j.comp_bytes) {
+                const u128u x = *(const u128u *)(ls + o);
+                store_upto16(L.u.tile + (at - base16) + o, ((uint64_t)x.b << 32) | x.a, ((uint64_t)x.d << 32) | x.c, n);
+            } else {
+                for (uint32_t k = 0; k < n; k++) L.u.tile[at - base16 + o + k] = ls[o + k];
+            }
+        }
     }
     if (tiled) {
         __syncthreads();
@@ -722,7 +789,7 @@ __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
 {
     uint32_t R0, R1;
     level_range(B, k, R0, R1);
-    const uint32_t G = gridDim.x, P = G < 8 ? G : 8;
+    const uint32_t G = gridDim.x, P = G < B.xcd_parts ? G : B.xcd_parts;
     const uint32_t x = blockIdx.x % P, w = blockIdx.x / P, W = (G - x + P - 1) / P;
     const uint64_t S = R1 > R0 ? R1 - R0 : 0;
     const uint32_t p0 = R0 + (uint32_t)(S * x / P), p1 = R0 + (uint32_t)(S * (x + 1) / P);
@@ -732,7 +799,7 @@ __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
         int32_t *sp[ROUND];
         uint32_t on[ROUND], dst[ROUND], src[ROUND], len[ROUND];
         load_records(B, k, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
-        run_records(ob, on, sp, dst, src, len);
+        run_records(ob, on, sp, dst, src, len, B.long_copy);
     }
 }
 
@@ -761,11 +828,11 @@ __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
         uint32_t on[ROUND], len[ROUND];
         const uint32_t r0 = hi_k ? min(lo_k + threadIdx.x, hi_k - 1) : 0;
         resolve_records(B, k, r0, NT_TAIL, lj, ob, on, sp, len);
-        run_records(ob, on, sp, dst, src, len);
+        run_records(ob, on, sp, dst, src, len, B.long_copy);
         for (uint32_t r = lo_k + ROUND * NT_TAIL + threadIdx.x;; r += ROUND * NT_TAIL) {
             if (__ballot(r < hi_k) == 0) break;
             load_records(B, k, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
-            run_records(ob, on, sp, dst, src, len);
+            run_records(ob, on, sp, dst, src, len, B.long_copy);
         }
         __syncthreads();
     }
@@ -803,7 +870,7 @@ struct PhaseScope {
     hipStream_t st;
     size_t i0 = 0;
     bool on;
-    PhaseScope(int p, hipStream_t s) : ph(p), st(s), on(g_timing.on)
+    PhaseScope(int p, hipStream_t s, bool timed = true) : ph(p), st(s), on(g_timing.on && timed)
     {
         if (!on) return;
         i0 = g_timing.used;
@@ -858,27 +925,40 @@ int hip_fail(hipError_t e)
     return ACEAPEX_E_HIP;
 }
 
-uint32_t level_wgs(uint64_t records)
+// The schedule of the level phase (aceapex_tuning).
+struct Tune {
+    uint32_t level_wg_max = LEVEL_WG_MAX, tail_level_max = TAIL_LEVEL_MAX;
+    uint32_t long_copy = LONG_COPY, xcd_parts = XCD_PARTS;
+};
+
+bool tune_valid(const Tune &t)
+{
+    return t.level_wg_max >= 1 && t.level_wg_max <= 65535 && t.long_copy >= 16 && t.long_copy <= (1u << 21) &&
+           t.xcd_parts >= 1 && t.xcd_parts <= 8;
+}
+
+uint32_t level_wgs(uint64_t records, const Tune &tn)
 {
     const uint64_t per_wg = (uint64_t)NT * ROUND;
-    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(LEVEL_WG_MAX, (records + per_wg - 1) / per_wg));
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tn.level_wg_max, (records + per_wg - 1) / per_wg));
 }
 
 // Level launches: one per level with records, sized to its count, and the
 // deep levels that hold few matches together in the tail workgroup.  counts
 // is null when the host does not know them (full-size launch per level).
-void launch_levels(const Batch &B, const uint64_t *counts, uint64_t n_seq, hipStream_t st)
+void launch_levels(const Batch &B, const uint64_t *counts, uint64_t n_seq, const Tune &tn, hipStream_t st,
+                   bool timed)
 {
-    PhaseScope ps(PH_LEVELS, st);
+    PhaseScope ps(PH_LEVELS, st, timed);
     uint32_t tail = B.max_level + 1;
     if (counts) {
-        while (tail > 1 && counts[tail - 1] <= TAIL_LEVEL_MAX) tail--;
+        while (tail > 1 && counts[tail - 1] <= tn.tail_level_max) tail--;
         if (B.max_level + 1 - tail < 2) tail = B.max_level + 1;
     }
     for (uint32_t k = 0; k < tail; k++) {
         const uint64_t cnt = counts ? counts[k] : n_seq;
         if (counts && !cnt) continue;
-        hipLaunchKernelGGL(k_level, dim3(level_wgs(cnt)), dim3(NT), 0, st, B, k);
+        hipLaunchKernelGGL(k_level, dim3(level_wgs(cnt, tn)), dim3(NT), 0, st, B, k);
     }
     if (tail <= B.max_level) hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
 }
@@ -947,6 +1027,9 @@ int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     B.n_chunks = in.n_chunks;
     B.max_level = in.max_level;
     B.n_seq = in.n_seq;
+    const Tune tn;
+    B.long_copy = tn.long_copy;
+    B.xcd_parts = tn.xcd_parts;
     {
         PhaseScope ps(PH_SETUP, st);
         hipLaunchKernelGGL(k_setup, dim3(std::max<uint32_t>(1, std::min<uint32_t>(in.n_blocks, 65535))), dim3(NT), 0,
@@ -960,7 +1043,7 @@ int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
         if (in.n_seq) {
             std::vector<uint64_t> cnt;
             if (s.h_levels) cnt.assign(s.h_levels, s.h_levels + in.max_level + 1);
-            launch_levels(B, s.h_levels ? cnt.data() : nullptr, in.n_seq, st);
+            launch_levels(B, s.h_levels ? cnt.data() : nullptr, in.n_seq, tn, st, true);
         }
     }
     hipError_t e = hipGetLastError();
@@ -1036,25 +1119,34 @@ int stage_buffer(size_t bytes, Staging *&out)
     return ACEAPEX_OK;
 }
 
-int launch_batch(const aceapex_desc *d, uint32_t n, uint8_t *ws, hipStream_t st)
+// One launch sequence of a batch: the kernel arguments and the level counts
+// the host schedule needs.
+struct Group {
+    Batch B;
+    std::vector<uint64_t> tot;  // matches per level over the group
+    uint64_t n_blocks = 0, n_chunks = 0, n_seq = 0;
+    uint32_t n = 0;
+};
+
+// Lay out the group d[0, n) in the workspace ws: the host tables (stream
+// table, per-(stream, level) slot ranges, per-level slot offsets) are written
+// to h, which holds ws_batch(d, n).staged bytes and must then be copied to
+// the start of ws; g receives the kernel arguments.
+void build_group(const aceapex_desc *d, uint32_t n, uint8_t *ws, uint8_t *h, Group &g)
 {
     const BatchLayout w = ws_batch(d, n);
-    Staging *sb = nullptr;
-    int rc = stage_buffer(w.staged, sb);
-    if (rc) return rc;
-    uint8_t *h = (uint8_t *)sb->p;
     Job *hj = (Job *)(h + w.jobs);
     uint32_t *lo = (uint32_t *)(h + w.rec_lo), *hi = (uint32_t *)(h + w.rec_hi), *llo = (uint32_t *)(h + w.level_lo);
     // per level: matches over the batch; then each stream's slots inside its level
-    std::vector<uint64_t> tot((size_t)w.max_level + 1, 0);
+    g.tot.assign((size_t)w.max_level + 1, 0);
     for (uint32_t i = 0; i < n; i++)
-        for (uint32_t k = 0; k <= d[i].s.info.max_level; k++) tot[k] += d[i].s.h_levels[k];
+        for (uint32_t k = 0; k <= d[i].s.info.max_level; k++) g.tot[k] += d[i].s.h_levels[k];
     std::vector<uint64_t> at((size_t)w.max_level + 1, 0);
     uint64_t acc = 0;
     for (uint32_t k = 0; k <= w.max_level; k++) {
         llo[k] = (uint32_t)acc;
         at[k] = acc;
-        acc += tot[k];
+        acc += g.tot[k];
     }
     llo[w.max_level + 1] = (uint32_t)acc;
     uint64_t c0 = 0, b0 = 0, lv0 = 0;
@@ -1072,12 +1164,7 @@ int launch_batch(const aceapex_desc *d, uint32_t n, uint8_t *ws, hipStream_t st)
         b0 += in.n_blocks;
         lv0 += (uint64_t)in.max_level + 1;
     }
-    hipError_t e = hipMemcpyAsync(ws, h, w.staged, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e);
-    if ((e = hipEventRecord(sb->ev, st)) != hipSuccess) return hip_fail(e);
-    sb->pending = true;
-
-    Batch B;
+    Batch &B = g.B;
     memset(&B, 0, sizeof B);
     B.jobs = (const Job *)(ws + w.jobs);
     B.blk_job = (uint32_t *)(ws + w.blk_job);
@@ -1092,17 +1179,45 @@ int launch_batch(const aceapex_desc *d, uint32_t n, uint8_t *ws, hipStream_t st)
     B.n_chunks = (uint32_t)w.n_chunks;
     B.max_level = w.max_level;
     B.n_seq = (uint32_t)w.n_seq;
+    g.n_blocks = w.n_blocks;
+    g.n_chunks = w.n_chunks;
+    g.n_seq = w.n_seq;
+    g.n = n;
+}
+
+// The kernels of one group (nothing else: no copy, no allocation, no
+// memset), so that the sequence can be captured into a graph.
+void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
+{
+    Batch B = g.B;
+    B.long_copy = tn.long_copy;
+    B.xcd_parts = tn.xcd_parts;
     {
-        PhaseScope ps(PH_SETUP, st);
-        hipLaunchKernelGGL(k_map, dim3(n), dim3(NT), 0, st, B);
-        const uint64_t g = std::max<uint64_t>(std::max<uint64_t>(1, n), std::min<uint64_t>(w.n_blocks, 65535));
-        hipLaunchKernelGGL(k_setup, dim3((uint32_t)g), dim3(NT), 0, st, B);
+        PhaseScope ps(PH_SETUP, st, timed);
+        hipLaunchKernelGGL(k_map, dim3(g.n), dim3(NT), 0, st, B);
+        const uint64_t gs = std::max<uint64_t>(std::max<uint64_t>(1, g.n), std::min<uint64_t>(g.n_blocks, 65535));
+        hipLaunchKernelGGL(k_setup, dim3((uint32_t)gs), dim3(NT), 0, st, B);
     }
-    if (w.n_chunks) {
-        PhaseScope ps(PH_PARSE, st);
-        hipLaunchKernelGGL(k_parse, dim3((uint32_t)w.n_chunks), dim3(NT), 0, st, B);
+    if (g.n_chunks) {
+        PhaseScope ps(PH_PARSE, st, timed);
+        hipLaunchKernelGGL(k_parse, dim3((uint32_t)g.n_chunks), dim3(NT), 0, st, B);
     }
-    if (w.n_seq) launch_levels(B, tot.data(), w.n_seq, st);
+    if (g.n_seq) launch_levels(B, g.tot.data(), g.n_seq, tn, st, timed);
+}
+
+int launch_batch(const aceapex_desc *d, uint32_t n, uint8_t *ws, hipStream_t st)
+{
+    const BatchLayout w = ws_batch(d, n);
+    Staging *sb = nullptr;
+    int rc = stage_buffer(w.staged, sb);
+    if (rc) return rc;
+    Group g;
+    build_group(d, n, ws, (uint8_t *)sb->p, g);
+    hipError_t e = hipMemcpyAsync(ws, sb->p, w.staged, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((e = hipEventRecord(sb->ev, st)) != hipSuccess) return hip_fail(e);
+    sb->pending = true;
+    enqueue_group(g, Tune(), st, true);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e);
     return ACEAPEX_OK;
@@ -1151,6 +1266,46 @@ size_t many_bytes(const aceapex_desc *d, uint32_t n)
     }
     for (uint32_t i = 0; i < n; i++) single += ws_single(d[i].s.info).total;
     return std::max(batched, single);
+}
+
+// A batch laid out once in its workspace; launches only enqueue kernels.
+struct PlanImpl {
+    std::vector<Group> groups;
+    Tune tune;
+    hipStream_t cap = nullptr;       // private stream the graph is captured on
+    hipGraphExec_t exec = nullptr;   // captured launch sequence, made on first use
+    int device = 0;
+};
+
+void plan_drop_graph(PlanImpl *p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    p->exec = nullptr;
+}
+
+Tune tune_from(const aceapex_tuning &t)
+{
+    Tune tn;
+    tn.level_wg_max = t.level_wg_max;
+    tn.tail_level_max = t.tail_level_max;
+    tn.long_copy = t.long_copy;
+    tn.xcd_parts = t.xcd_parts;
+    return tn;
+}
+
+void tune_to(const Tune &tn, aceapex_tuning *t)
+{
+    t->level_wg_max = tn.level_wg_max;
+    t->tail_level_max = tn.tail_level_max;
+    t->long_copy = tn.long_copy;
+    t->xcd_parts = tn.xcd_parts;
+}
+
+int enqueue_plan(const PlanImpl *p, const Tune &tn, hipStream_t st, bool timed)
+{
+    for (const Group &g : p->groups) enqueue_group(g, tn, st, timed);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ACEAPEX_OK : hip_fail(e);
 }
 
 }  // namespace
@@ -1264,6 +1419,184 @@ const char *aceapex_strerror(int code)
 }
 
 int aceapex_last_hip_error(void) { return g_last_hip; }
+
+void aceapex_tuning_defaults(aceapex_tuning *t)
+{
+    if (t) tune_to(Tune(), t);
+}
+
+int aceapex_plan_create(const aceapex_desc *h_descs, uint32_t n, void *d_workspace, size_t ws_bytes,
+                        const aceapex_tuning *tuning, void *hip_stream, aceapex_plan **plan)
+{
+    if (!plan || (!h_descs && n)) return ACEAPEX_E_INVAL;
+    *plan = nullptr;
+    for (uint32_t i = 0; i < n; i++) {
+        int rc = check_stream_args(&h_descs[i].s, h_descs[i].d_out, h_descs[i].out_capacity);
+        if (rc) return rc;
+        if (!h_descs[i].s.h_levels) return ACEAPEX_E_INVAL;
+    }
+    if (n && (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < many_bytes(h_descs, n)))
+        return ACEAPEX_E_WORKSPACE;
+    Tune tn;
+    if (tuning) {
+        tn = tune_from(*tuning);
+        if (!tune_valid(tn)) return ACEAPEX_E_INVAL;
+    }
+    PlanImpl *p = new (std::nothrow) PlanImpl;
+    if (!p) return ACEAPEX_E_NOMEM;
+    p->tune = tn;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e);
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint8_t *ws = (uint8_t *)d_workspace;
+    std::vector<uint8_t> h;
+    for (uint32_t i = 0, m; i < n; i += m) {
+        m = group_size(h_descs + i, n - i);
+        const BatchLayout w = ws_batch(h_descs + i, m);
+        h.assign(w.staged, 0);
+        Group g;
+        build_group(h_descs + i, m, ws, h.data(), g);
+        if ((e = hipMemcpyAsync(ws, h.data(), w.staged, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess) {
+            delete p;
+            return hip_fail(e);
+        }
+        p->groups.push_back(std::move(g));
+        ws += w.total;
+    }
+    *plan = (aceapex_plan *)p;
+    return ACEAPEX_OK;
+}
+
+int aceapex_plan_launch(aceapex_plan *plan, void *hip_stream)
+{
+    PlanImpl *p = (PlanImpl *)plan;
+    if (!p) return ACEAPEX_E_INVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_fail(e);
+    return enqueue_plan(p, p->tune, st, cs == hipStreamCaptureStatusNone);
+}
+
+int aceapex_plan_launch_graph(aceapex_plan *plan, void *hip_stream)
+{
+    PlanImpl *p = (PlanImpl *)plan;
+    if (!p) return ACEAPEX_E_INVAL;
+    hipError_t e;
+    if (!p->exec) {
+        if (!p->cap && (e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e);
+        for (const Group &g : p->groups) enqueue_group(g, p->tune, p->cap, false);
+        hipGraph_t graph = nullptr;
+        const hipError_t le = hipGetLastError();
+        e = hipStreamEndCapture(p->cap, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le != hipSuccess ? le : e);
+        }
+        e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            p->exec = nullptr;
+            return hip_fail(e);
+        }
+    }
+    if ((e = hipGraphLaunch(p->exec, (hipStream_t)hip_stream)) != hipSuccess) return hip_fail(e);
+    return ACEAPEX_OK;
+}
+
+int aceapex_plan_set_tuning(aceapex_plan *plan, const aceapex_tuning *tuning)
+{
+    PlanImpl *p = (PlanImpl *)plan;
+    if (!p || !tuning) return ACEAPEX_E_INVAL;
+    const Tune tn = tune_from(*tuning);
+    if (!tune_valid(tn)) return ACEAPEX_E_INVAL;
+    p->tune = tn;
+    plan_drop_graph(p);
+    return ACEAPEX_OK;
+}
+
+int aceapex_plan_get_tuning(const aceapex_plan *plan, aceapex_tuning *tuning)
+{
+    const PlanImpl *p = (const PlanImpl *)plan;
+    if (!p || !tuning) return ACEAPEX_E_INVAL;
+    tune_to(p->tune, tuning);
+    return ACEAPEX_OK;
+}
+
+int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceapex_tuning *best)
+{
+    PlanImpl *p = (PlanImpl *)plan;
+    if (!p) return ACEAPEX_E_INVAL;
+    reps = std::max<uint32_t>(1, reps);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e);
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e);
+    }
+    // time of one launch of the plan under tn: one warm-up, then the mean of reps
+    auto timed_run = [&](const Tune &tn, float &ms) -> int {
+        int rc = enqueue_plan(p, tn, st, false);
+        if (rc) return rc;
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) return hip_fail(e);
+        for (uint32_t r = 0; r < reps; r++)
+            if ((rc = enqueue_plan(p, tn, st, false))) return rc;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+            return hip_fail(e);
+        ms /= (float)reps;
+        return ACEAPEX_OK;
+    };
+    // coordinate descent over the knobs, one at a time, from the current schedule
+    static const uint32_t wg[] = {512, 1024, 2048, 4096, 8192};
+    static const uint32_t tail[] = {0, 2048, 8192, 32768};
+    static const uint32_t longc[] = {32, 64, 128, 512};
+    static const uint32_t parts[] = {1, 8};
+    Tune cur = p->tune;
+    float best_ms = 0.f;
+    int rc = timed_run(cur, best_ms);
+    auto sweep = [&](uint32_t Tune::*knob, const uint32_t *vals, size_t nv) {
+        for (size_t i = 0; i < nv && !rc; i++) {
+            if (cur.*knob == vals[i]) continue;
+            Tune t = cur;
+            t.*knob = vals[i];
+            float ms = 0.f;
+            rc = timed_run(t, ms);
+            if (!rc && ms < 0.99f * best_ms) {  // keep a change only when it is clearly faster
+                best_ms = ms;
+                cur = t;
+            }
+        }
+    };
+    sweep(&Tune::level_wg_max, wg, sizeof wg / sizeof wg[0]);
+    sweep(&Tune::tail_level_max, tail, sizeof tail / sizeof tail[0]);
+    sweep(&Tune::long_copy, longc, sizeof longc / sizeof longc[0]);
+    sweep(&Tune::xcd_parts, parts, sizeof parts / sizeof parts[0]);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    p->tune = cur;
+    plan_drop_graph(p);
+    if (best) tune_to(cur, best);
+    return ACEAPEX_OK;
+}
+
+void aceapex_plan_destroy(aceapex_plan *plan)
+{
+    PlanImpl *p = (PlanImpl *)plan;
+    if (!p) return;
+    plan_drop_graph(p);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    delete p;
+}
 
 int aceapex_timing(int enable)
 {

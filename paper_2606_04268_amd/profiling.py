@@ -1,0 +1,184 @@
+"""HBM traffic of the decoder's kernels from rocprofv3 counters.
+
+Two helpers for the counter runs whose summaries sit in ``profiles/``:
+
+``python -m paper_2606_04268_amd.profiling copycal``
+    A plain device copy of 1 GiB (three times), run under
+    ``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` to calibrate the
+    counters: the copy reads and writes exactly 1 GiB, so
+    ``1 GiB / counter`` is the factor that turns each counter into bytes.
+
+``python -m paper_2606_04268_amd.profiling summarize ...``
+    Reads the counter CSVs of a decode run and of the copy run and writes a
+    Markdown summary: per decode, the scaled HBM bytes fetched and written by
+    each kernel group (setup, parse, levels) beside its algorithmic bytes.
+    The summary ends with one machine-readable line (an HTML comment holding
+    JSON) that ``bench.py`` reads to fill ``roofline.traffic``, together with
+    the SHA-256 of the kernel source it was measured on, so that a changed
+    kernel reports no stale traffic.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "aceapex.hip")
+GIB_KIB = 1 << 20  # counters are reported in KiB
+
+GROUP_OF = {"k_map": "setup", "k_setup": "setup", "k_parse": "parse", "k_level": "levels", "k_tail": "levels"}
+
+
+def source_sha256() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def copycal():
+    import torch
+
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 3 x 1 GiB", flush=True)
+
+
+def _rows(d: str):
+    path = d if d.endswith(".csv") else os.path.join(d, "run_counter_collection.csv")
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    m = re.search(r"::(k_\w+)\(", name)
+    return m.group(1) if m else name.split("(")[0][:60]
+
+
+def calibration(d: str, counter: str) -> float:
+    """Bytes per counter unit: 1 GiB over what the counter read for the copy
+    dispatches of 1 GiB (the largest dispatches of the copy run)."""
+    vals = [float(r["Counter_Value"]) for r in _rows(d) if r["Counter_Name"] == counter
+            and "copyBuffer" in r["Kernel_Name"]]
+    if not vals:
+        raise SystemExit(f"no copy dispatch with {counter} in {d}")
+    v = max(vals)
+    return GIB_KIB / v * 1024.0
+
+
+def per_decode(d: str, counter: str):
+    """Mean counter value (KiB) per decode for each kernel group; a decode
+    starts at each k_setup dispatch (preceded by k_map in a batch)."""
+    decodes = []
+    cur = None
+    for r in sorted(_rows(d), key=lambda r: int(r["Dispatch_Id"])):
+        if r["Counter_Name"] != counter:
+            continue
+        k = _short(r["Kernel_Name"])
+        g = GROUP_OF.get(k)
+        if g is None:
+            continue
+        if k == "k_setup" and (cur is None or cur.get("_parsed")):
+            cur = {"setup": 0.0, "parse": 0.0, "levels": 0.0, "dispatches": 0}
+            decodes.append(cur)
+        if cur is None:
+            continue
+        cur[g] += float(r["Counter_Value"])
+        cur["dispatches"] += 1
+        if k == "k_parse":
+            cur["_parsed"] = True
+    if not decodes:
+        raise SystemExit(f"no decode found in {d}")
+    out = {g: sum(x[g] for x in decodes) / len(decodes) for g in ("setup", "parse", "levels")}
+    out["decodes"] = len(decodes)
+    out["dispatches_per_decode"] = decodes[-1]["dispatches"]
+    return out
+
+
+def summarize(args):
+    import sys
+
+    sys.path.insert(0, os.path.dirname(HERE))
+    ff = calibration(args.cal_fetch, "FETCH_SIZE")
+    fw = calibration(args.cal_write, "WRITE_SIZE")
+    fetch = per_decode(args.fetch, "FETCH_SIZE")
+    write = per_decode(args.write, "WRITE_SIZE")
+    alg = json.loads(args.algorithmic) if args.algorithmic else {}
+    groups = {}
+    for g in ("setup", "parse", "levels"):
+        fb = fetch[g] * ff
+        wb = write[g] * fw
+        groups[g] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "traffic_bytes": round(fb + wb)}
+        if g in alg:
+            groups[g]["algorithmic_bytes"] = alg[g]
+            groups[g]["traffic_over_algorithmic"] = round((fb + wb) / alg[g], 3) if alg[g] else None
+    lines = [f"# HBM traffic per decode: {args.title}", ""]
+    lines += [f"Workload: {args.workload}", ""]
+    lines += ["Counters (KiB per dispatch) are scaled by what the same counter reads for a plain",
+              f"1 GiB device copy: FETCH_SIZE x {ff / 1024:.3f} KiB-to-KiB, WRITE_SIZE x {fw / 1024:.3f}.",
+              f"Decodes in the run: {fetch['decodes']}; kernel dispatches per decode: "
+              f"{fetch['dispatches_per_decode']}.", ""]
+    lines += ["Commands (from the repository root):", "", "```"]
+    lines += args.command
+    lines += ["```", ""]
+    lines += ["| Kernel group | Fetched (MB) | Written (MB) | Traffic (MB) | Algorithmic (MB) | Traffic / algorithmic |",
+              "|---|---|---|---|---|---|"]
+    for g, v in groups.items():
+        a = v.get("algorithmic_bytes")
+        lines.append(f"| {g} | {v['fetch_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "
+                     f"{v['traffic_bytes'] / 1e6:.1f} | {a / 1e6:.1f} | {v.get('traffic_over_algorithmic')} |"
+                     if a is not None else
+                     f"| {g} | {v['fetch_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "
+                     f"{v['traffic_bytes'] / 1e6:.1f} | - | - |")
+    rec = {"workload": args.key, "source_sha256": source_sha256(), "groups": groups}
+    lines += ["", f"<!-- traffic: {json.dumps(rec, sort_keys=True)} -->", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def load_traffic(path: str):
+    """The traffic record of a summary, or None when it is absent or was
+    measured on another version of the kernel source."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        m = re.search(r"<!-- traffic: (\{.*\}) -->", f.read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    return rec if rec.get("source_sha256") == source_sha256() else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("copycal")
+    s = sub.add_parser("summarize")
+    s.add_argument("--fetch", required=True)
+    s.add_argument("--write", required=True)
+    s.add_argument("--cal-fetch", required=True)
+    s.add_argument("--cal-write", required=True)
+    s.add_argument("--algorithmic", default="", help="JSON {group: algorithmic bytes per decode}")
+    s.add_argument("--title", required=True)
+    s.add_argument("--workload", required=True)
+    s.add_argument("--key", required=True)
+    s.add_argument("--command", action="append", default=[])
+    s.add_argument("--out", required=True)
+    args = ap.parse_args()
+    if args.cmd == "copycal":
+        copycal()
+    else:
+        summarize(args)
+
+
+if __name__ == "__main__":
+    main()

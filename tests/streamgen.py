@@ -12,13 +12,16 @@ from __future__ import annotations
 import numpy as np
 
 
-def _varint(v: int) -> bytes:
+def _varint(v: int, width: int = 0) -> bytes:
+    """LEB128 of v in at least `width` bytes (zero groups with the continuation
+    bit pad a short value: a valid, non-minimal encoding)."""
     out = bytearray()
     while True:
         c = v & 0x7F
         v >>= 7
-        out.append(c | (0x80 if v else 0))
-        if not v:
+        more = bool(v) or len(out) + 1 < width
+        out.append(c | (0x80 if more else 0))
+        if not more:
             return bytes(out)
 
 
@@ -84,8 +87,19 @@ def random_tokens(rng: np.random.Generator, n: int, block_log2: int, min_match: 
 
 def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
           chunk_log2: int = 10, levels=None, flags: int = 8, max_depth: int = 0,
-          max_level=None, n_deep=None, level_counts=None) -> np.ndarray:
-    """Serialize token lists into the stream layout (levels from the definition by default)."""
+          max_level=None, n_deep=None, level_counts=None, varint_width=None) -> np.ndarray:
+    """Serialize token lists into the stream layout (levels from the definition by default).
+
+    varint_width: None for minimal LEB128; an int w to pad every value to at
+    least w bytes; a numpy Generator to draw each value's width from 1..4.
+    """
+    def vw():
+        if varint_width is None:
+            return 0
+        if isinstance(varint_width, int):
+            return varint_width
+        return int(varint_width.integers(1, 5))
+
     decoded, exact = execute(blocks, lits, n, block_log2)
     if levels is None:
         levels = exact
@@ -105,20 +119,20 @@ def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
         for i, (r, m, s) in enumerate(seqs):
             if i % K == 0:
                 chunks.append((len(cmd), len(ln), len(lv), len(lit), p))
-            cmd += _varint(r)
+            cmd += _varint(r, vw())
             lit += lits[li:li + r]
             li += r
             p += r
-            ln += _varint(m - min_match)
+            ln += _varint(m - min_match, vw())
             off += int(s).to_bytes(4, "little")
-            lv += _varint(levels[mi])
+            lv += _varint(levels[mi], vw())
             bmax = max(bmax, levels[mi])
             deep += levels[mi] > 0
             mi += 1
             p += m
         if not seqs:
             chunks.append((0, 0, 0, 0, 0))
-        cmd += _varint(trail)
+        cmd += _varint(trail, vw())
         lit += lits[li:li + trail]
         li += trail
         gmax = max(gmax, bmax)

@@ -102,3 +102,30 @@ def test_level_table_matches_tokens():
     bad[at] ^= 1
     with pytest.raises(_abi.AceapexError):
         _abi.level_table(bad, info)
+
+
+def test_plan_argument_errors_need_no_gpu():
+    s = oracle.encode(synth.markov(5000, 1), block_log2=12)
+    info = _abi.probe(s)
+    levels = _abi.level_table(s, info)
+    t = _abi.tuning_defaults()
+    assert (t.level_wg_max, t.tail_level_max, t.long_copy, t.xcd_parts) == (2048, 8192, 128, 8)
+    lib = _abi.load()
+    h = ctypes.c_void_p()
+    with_table = _abi.Desc(_abi.Stream(16, info, levels), 4096, info.decoded_bytes, 0)
+    without = _abi.Desc(_abi.Stream(16, info, None), 4096, info.decoded_bytes, 0)
+    arr = (_abi.Desc * 1)(with_table)
+    ws = _abi.workspace_bytes([with_table])
+    assert lib.aceapex_plan_create(arr, 1, 4096, ws, None, None, None) == _abi.E_INVAL  # no plan pointer
+    assert lib.aceapex_plan_create((_abi.Desc * 1)(without), 1, 4096, ws, None, None, ctypes.byref(h)) == _abi.E_INVAL
+    assert lib.aceapex_plan_create(arr, 1, 4096, ws - 256, None, None, ctypes.byref(h)) == _abi.E_WORKSPACE
+    for k, v in [("level_wg_max", 0), ("level_wg_max", 65536), ("long_copy", 8), ("xcd_parts", 0), ("xcd_parts", 9)]:
+        bad = _abi.tuning_defaults()
+        setattr(bad, k, v)
+        assert lib.aceapex_plan_create(arr, 1, 4096, ws, ctypes.byref(bad), None, ctypes.byref(h)) == _abi.E_INVAL, k
+    assert h.value is None
+    assert lib.aceapex_plan_launch(None, None) == _abi.E_INVAL
+    assert lib.aceapex_plan_launch_graph(None, None) == _abi.E_INVAL
+    assert lib.aceapex_plan_set_tuning(None, ctypes.byref(t)) == _abi.E_INVAL
+    assert lib.aceapex_plan_tune(None, None, 1, None) == _abi.E_INVAL
+    lib.aceapex_plan_destroy(None)

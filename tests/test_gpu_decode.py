@@ -89,6 +89,25 @@ def test_random_token_streams(seed):
     parity(np.frombuffer(want, np.uint8), s, f"tokens seed={seed} bl={bl}")
 
 
+@pytest.mark.parametrize("width", [4, "random"])
+def test_padded_varints(width):
+    """Non-minimal LEB128: every value padded to 4 bytes fills a full chunk's
+    slices to 4096 bytes (the largest the workgroup decoder takes) and a
+    chunk that also holds the trailing run to 4100 (decoded one wave per
+    slice); random widths mix value lengths inside every window."""
+    rng = np.random.default_rng(23)
+    w = 4 if width == 4 else np.random.default_rng(29)
+    m = 2048  # two full chunks of 1024 sequences; the second holds the trailing run
+    blocks = [([(4, 4, 0)] + [(1, 4, int(rng.integers(0, 4))) for _ in range(m - 1)], 3)]
+    n = 8 + 5 * (m - 1) + 3
+    lits = bytes(rng.integers(0, 256, size=n, dtype=np.uint8))
+    s, want = streamgen.build(blocks, lits, n, block_log2=16, chunk_log2=10, varint_width=w)
+    parity(np.frombuffer(want, np.uint8), s, f"padded varints width={width}")
+    blocks, lits = streamgen.random_tokens(rng, 200_000, 16, max_len=300, p_match=0.8)
+    s, want = streamgen.build(blocks, lits, 200_000, block_log2=16, chunk_log2=10, varint_width=w)
+    parity(np.frombuffer(want, np.uint8), s, f"padded varints random tokens width={width}")
+
+
 def test_doubling_string_long_matches():
     u = np.random.default_rng(7).permutation(256)[:16].astype(np.uint8).tobytes()
     x = u * (1 << 16)  # 1 MiB of one repeated 16-byte unit: long matches, deep levels
@@ -120,6 +139,23 @@ def test_multiple_of_chunk_size():
     n = 8 * 8 + 3
     s, want = streamgen.build(blocks, lits, n, block_log2=8, chunk_log2=2)
     parity(np.frombuffer(want, np.uint8), s, "nseq%K==0")
+
+
+@pytest.mark.parametrize("run", [1, 200], ids=["one_byte_runs", "two_byte_runs"])
+@pytest.mark.parametrize("trail", [0, 5, 40, 20000], ids=lambda t: f"trail{t}")
+def test_full_chunk_holding_the_trailing_run(run, trail):
+    """A block of exactly 2 x 1024 sequences at the largest chunk size: its
+    last chunk holds 1024 sequences plus the trailing run, one command more
+    than the workgroup's threads cover.  Runs of 200 bytes take the
+    workgroup varint decoder, runs of 1 the one-byte path; a trailing run of
+    20000 bytes makes the chunk's span exceed the LDS tile."""
+    rng = np.random.default_rng(run * 100 + trail)
+    m = 2048
+    seqs = [(4, 4, 0)] + [(run, 4, int(rng.integers(0, 4))) for _ in range(m - 1)]
+    n = 8 + (run + 4) * (m - 1) + trail
+    lits = bytes(rng.integers(0, 256, size=n, dtype=np.uint8))
+    s, want = streamgen.build([(seqs, trail)], lits, n, block_log2=20, chunk_log2=10)
+    parity(np.frombuffer(want, np.uint8), s, f"full last chunk run={run} trail={trail}")
 
 
 def test_decode_many_matches_single():

@@ -204,6 +204,22 @@ def test_random_token_streams(seed):
         assert oracle.decode_mt(s, T).tobytes() == want
 
 
+@pytest.mark.parametrize("width", [2, 4, "random"])
+def test_padded_varints_decode_the_same(width):
+    """LEB128 values padded with zero continuation groups (non-minimal, at most
+    4 bytes) are valid and decode like the minimal encoding."""
+    rng = np.random.default_rng(17)
+    n = 20_000
+    blocks, lits = streamgen.random_tokens(rng, n, 12, max_len=300, p_match=0.7)
+    w = np.random.default_rng(5) if width == "random" else width
+    s, want = streamgen.build(blocks, lits, n, block_log2=12, chunk_log2=6, varint_width=w)
+    s0, want0 = streamgen.build(blocks, lits, n, block_log2=12, chunk_log2=6)
+    assert want == want0 and s.size > s0.size
+    assert oracle.decode(s).tobytes() == want
+    assert oracle.refdec(s) == want
+    assert oracle.check(np.frombuffer(want, np.uint8), s).level_mismatch == 0
+
+
 def test_edge_cases():
     for x in [b"", b"a", b"abc", b"abcd", b"aaaaaaaa", bytes(range(256)) * 3]:
         for o in [dict(), dict(block_log2=3, chunk_log2=0), dict(flatten=1, block_log2=4)]:
