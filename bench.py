@@ -133,9 +133,14 @@ def build_pool(recipe):
     t0 = time.perf_counter()
     order = sorted(range(len(recipe)), key=lambda i: -recipe[i][1])
     res = [None] * len(recipe)
+    done_bytes, last = 0, time.perf_counter()
     with ThreadPoolExecutor(workers) as ex:
         for i, r in zip(order, ex.map(one, [recipe[i] for i in order])):
             res[i] = r
+            done_bytes += recipe[i][1]
+            if time.perf_counter() - last > 10:
+                last = time.perf_counter()
+                log(f"pool: {done_bytes / 1e9:.2f} GB encoded after {last - t0:.0f}s")
     tot = sum(r[1] for r in recipe)
     log(f"pool: {len(recipe)} streams, {tot / 1e9:.2f} GB decoded, generated and encoded in "
         f"{time.perf_counter() - t0:.1f}s on {workers} workers")
