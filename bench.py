@@ -346,6 +346,39 @@ def run_served(args):
     print(json.dumps(line), flush=True)
 
 
+def plan_graph_leg(ds, out, ws, status, stream, x_dev, args) -> dict:
+    """The same decode through a plan (laid out once, schedule autotuned),
+    replayed as a captured HIP graph; timed like the main line and checked."""
+    import torch
+
+    import paper_2606_04268_amd as ax
+
+    plan = ax.Plan([ds], outs=[out], statuses=status, workspace=ws, stream=stream)
+    try:
+        tuned = plan.tune(reps=3, stream=stream)
+        out.fill_(0xA5)
+        plan.launch(stream=stream, graph=True)
+        torch.cuda.synchronize()
+        ax.check_status(status)
+        assert torch.equal(out, x_dev), "plan decode differs from the original bytes"
+        for _ in range(args.warmup):
+            plan.launch(stream=stream, graph=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.launch(stream=stream, graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        ax.check_status(status)
+        assert torch.equal(out, x_dev), "plan decode differs from the original bytes"
+    finally:
+        plan.close()
+    log(f"plan + graph, tuned {tuned}: {ms:.4f} ms per decode")
+    return {"ms_per_step": round(ms, 4), "gbps": round(ds.n / (ms * 1e-3) / 1e9, 3), "tuning": tuned}
+
+
 def print_algorithmic(args):
     """Algorithmic bytes per kernel group of the workload's stream (JSON), for
     the traffic summaries of the counter runs."""
@@ -487,6 +520,7 @@ def main():
         "kernel_groups": {k: {"ms_per_launch": round(v["ms_per_launch"], 5), "launches": v["launches"]}
                           for k, v in per_group.items()},
     }
+    line["plan_graph_tuned"] = plan_graph_leg(ds, out, ws, status, stream, x_dev, args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(s, x)
     print(json.dumps(line), flush=True)

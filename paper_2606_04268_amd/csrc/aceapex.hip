@@ -246,15 +246,14 @@ __device__ __forceinline__ void fetch_records(const Batch &B, uint32_t r0, uint3
     }
 }
 
-// The stream of each fetched record: its output, size and status; a record
-// in a slot that a batched stream did not fill in this decode yields len = 0.
-__device__ __forceinline__ void resolve_records(const Batch &B, uint32_t k, uint32_t r0, uint32_t stride,
-                                                const uint32_t *lj, uint8_t **ob, uint32_t *on, int32_t **sp,
-                                                uint32_t *len)
+// The stream of each fetched record: its output, size and status.  In a
+// batch every slot of a level was filled in this decode or given length 0 by
+// k_seal, so the stream index carried by the record is all that is needed.
+__device__ __forceinline__ void resolve_records(const Batch &B, const uint32_t *lj, uint8_t **ob, uint32_t *on,
+                                                int32_t **sp, uint32_t *len)
 {
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
-        const uint32_t i = r0 + u * stride;
         len[u] = lj[u] & LEN_MASK;
         if (!B.jobs) {
             ob[u] = B.one.out;
@@ -267,12 +266,9 @@ __device__ __forceinline__ void resolve_records(const Batch &B, uint32_t k, uint
             sp[u] = nullptr;
             if (len[u] && s < B.n_jobs) {
                 const Job &j = B.jobs[s];
-                const uint32_t e = j.lv0 + k;
-                if (k <= j.max_level && i >= B.rec_lo[e] && i < min(B.cursor[e], B.rec_hi[e])) {
-                    ob[u] = j.out;
-                    on[u] = j.n;
-                    sp[u] = j.status;
-                }
+                ob[u] = j.out;
+                on[u] = j.n;
+                sp[u] = j.status;
             }
             if (!ob[u]) len[u] = 0;
         }
@@ -280,13 +276,13 @@ __device__ __forceinline__ void resolve_records(const Batch &B, uint32_t k, uint
 }
 
 // Fetch and resolve ROUND records (see fetch_records, resolve_records).
-__device__ __forceinline__ void load_records(const Batch &B, uint32_t k, uint32_t r0, uint32_t stride,
+__device__ __forceinline__ void load_records(const Batch &B, uint32_t r0, uint32_t stride,
                                              uint32_t r_end, uint8_t **ob, uint32_t *on, int32_t **sp,
                                              uint32_t *dst, uint32_t *src, uint32_t *len)
 {
     uint32_t lj[ROUND];
     fetch_records(B, r0, stride, r_end, dst, src, lj);
-    resolve_records(B, k, r0, stride, lj, ob, on, sp, len);
+    resolve_records(B, lj, ob, on, sp, len);
 }
 
 // ------------------------------------------------------------------- scans
@@ -780,6 +776,24 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
     if (bad) fail(j, ACEAPEX_E_CORRUPT);
 }
 
+// --------------------------------------------------------------- k_seal
+
+// Batches: after the parse, every record slot of a stream that the parse did
+// not fill in this decode (possible only for a corrupt stream) gets length 0,
+// so that the level launches may run every slot of a level without checking
+// which decode wrote it.  One workgroup per stream.
+__global__ void __launch_bounds__(NT) k_seal(Batch B)
+{
+    const Job &j = B.jobs[blockIdx.x];
+    for (uint32_t i = 0; i <= j.max_level; i++) {
+        const uint32_t e = j.lv0 + i;
+        const uint32_t hi = B.rec_hi[e], filled = min(max(B.cursor[e], B.rec_lo[e]), hi);
+        if (filled == hi) continue;
+        for (uint32_t r = filled + threadIdx.x; r < hi; r += NT) B.recs[3ull * r + 2] = 0;
+        if (threadIdx.x == 0) fail(j, ACEAPEX_E_CORRUPT);
+    }
+}
+
 // --------------------------------------------------------------- k_level
 
 // The level's slots are split into one contiguous part per XCD; the
@@ -798,7 +812,7 @@ __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
         uint8_t *ob[ROUND];
         int32_t *sp[ROUND];
         uint32_t on[ROUND], dst[ROUND], src[ROUND], len[ROUND];
-        load_records(B, k, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
+        load_records(B, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
         run_records(ob, on, sp, dst, src, len, B.long_copy);
     }
 }
@@ -826,12 +840,11 @@ __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
         uint8_t *ob[ROUND];
         int32_t *sp[ROUND];
         uint32_t on[ROUND], len[ROUND];
-        const uint32_t r0 = hi_k ? min(lo_k + threadIdx.x, hi_k - 1) : 0;
-        resolve_records(B, k, r0, NT_TAIL, lj, ob, on, sp, len);
+        resolve_records(B, lj, ob, on, sp, len);
         run_records(ob, on, sp, dst, src, len, B.long_copy);
         for (uint32_t r = lo_k + ROUND * NT_TAIL + threadIdx.x;; r += ROUND * NT_TAIL) {
             if (__ballot(r < hi_k) == 0) break;
-            load_records(B, k, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
+            load_records(B, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
             run_records(ob, on, sp, dst, src, len, B.long_copy);
         }
         __syncthreads();
@@ -1202,7 +1215,13 @@ void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
         PhaseScope ps(PH_PARSE, st, timed);
         hipLaunchKernelGGL(k_parse, dim3((uint32_t)g.n_chunks), dim3(NT), 0, st, B);
     }
-    if (g.n_seq) launch_levels(B, g.tot.data(), g.n_seq, tn, st, timed);
+    if (g.n_seq) {
+        {
+            PhaseScope ps(PH_PARSE, st, timed);
+            hipLaunchKernelGGL(k_seal, dim3(g.n), dim3(NT), 0, st, B);
+        }
+        launch_levels(B, g.tot.data(), g.n_seq, tn, st, timed);
+    }
 }
 
 int launch_batch(const aceapex_desc *d, uint32_t n, uint8_t *ws, hipStream_t st)
