@@ -63,6 +63,7 @@ constexpr uint32_t LEVEL_WG_MAX = 2048;     // workgroups of one level launch, a
 constexpr uint32_t TAIL_LEVEL_MAX = 8192;   // levels with at most this many matches may join the tail
 constexpr uint32_t XCD_PARTS = 8;           // contiguous parts of a level's records, one per XCD
 constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
+constexpr uint32_t STAGE_BYTES = 7680;      // a chunk's literals staged in LDS by k_parse, at most
 constexpr uint64_t CHUNKS_MAX = 1ull << 24;  // chunks of one launch sequence (the k_parse grid), at most
 
 typedef uint16_t u16u __attribute__((aligned(1)));
@@ -539,6 +540,7 @@ struct ParseLds {
         } v;
         uint8_t tile[TILE_BYTES];      // after the scan: the chunk's output span, literals in place
     } u;
+    uint32_t stage[STAGE_BYTES / 4 + 4];  // the chunk's literal bytes from a 16-byte boundary
     uint32_t lcount[LH];         // matches of the chunk per level (levels < LH)
     uint32_t lbase[LH];          // record slot reserved for them
     uint64_t tmp[NT / 64];
@@ -575,6 +577,32 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
     const uint32_t ncmd = ns + (d.nseq_last >> 31);
     const bool one_byte = d.cmd_n == ncmd && d.len_n == ns && d.lvl_n == ns;
     const uint32_t e0 = t * PER;
+
+    // Literal placement.  When the chunk's output span fits the LDS tile, the
+    // runs are placed in the tile and the whole span is written with aligned
+    // 16-byte stores (its match bytes are written later by the level
+    // launches).  With matches of at least 3 bytes between runs, no 4-byte
+    // word of the output holds literal bytes of two runs, so a run is placed
+    // as the whole aligned words that cover it; their other bytes lie in the
+    // neighbouring matches.  The chunk's literal bytes, from the 16-byte
+    // boundary at or below lit_at - 4, are first copied into LDS by direct
+    // global-to-LDS loads issued here and awaited before the scan.
+    const uint32_t base16 = d.out_base & ~15u;
+    const uint32_t span_end = d.out_base + d.out_len;
+    const bool tiled = span_end - base16 <= TILE_BYTES;
+    const bool words = tiled && j.min_match >= 3;
+    const uint64_t la = ((uint64_t)d.lit_at - 4) & ~(uint64_t)15;
+    const uint64_t lend = ((uint64_t)d.lit_at + d.lit_n + 15) & ~(uint64_t)15;
+    const bool staged = words && d.lit_at >= 4 && lend - la <= STAGE_BYTES && lend <= j.comp_bytes;
+    if (staged) {
+        const uint32_t nblk = (uint32_t)((lend - la) >> 4);
+        for (uint32_t b0 = 64 * wave; b0 < nblk; b0 += NT) {  // b0: the wave's first 16-byte block
+            if (b0 + (t & 63) < nblk)
+                __builtin_amdgcn_global_load_lds(j.comp + la + 16ull * (b0 + (t & 63)),
+                                                 (__attribute__((address_space(3))) void *)((uint8_t *)L.stage + 16 * b0),
+                                                 16, 0, 0);
+        }
+    }
     // a full chunk (NT * PER sequences) that also holds its block's trailing
     // run: that run is the command past every thread's range.  Every thread
     // reads it (it ends the chunk's span and its literals); the last thread
@@ -637,6 +665,7 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
     rt = __builtin_amdgcn_readfirstlane(rt);
     if (rt > d.out_len) bad = true;
     if (t == NT - 1) acc += ((uint64_t)rt << 32) | rt;
+    if (staged) __builtin_amdgcn_s_waitcnt(0);  // this thread's staging loads; the scan's barrier publishes them
     uint64_t tot;
     const uint64_t ex = wg_excl_scan64(bad ? 0 : acc, L.tmp, tot);
     if (bad) L.bad = 1;
@@ -646,24 +675,18 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
         return;
     }
 
-    // Literal runs to their output positions.  When the chunk's output span
-    // fits the LDS tile, the runs are placed in the tile and the whole span is
-    // written with aligned 16-byte stores (its match bytes are written later by
-    // the level launches); otherwise every run is copied on its own.
-    const uint32_t base16 = d.out_base & ~15u;
-    const uint32_t span_end = d.out_base + d.out_len;
-    const bool tiled = span_end - base16 <= TILE_BYTES;
     uint32_t pos = d.out_base + (uint32_t)(ex >> 32), lq = (uint32_t)ex;
     uint32_t dst[PER], rank[PER];
-    // With matches of at least 3 bytes between runs, no 4-byte word of the
-    // output holds literal bytes of two runs.  A run is then placed as the
-    // whole aligned words that cover it (aligned LDS stores, no partial ones);
-    // their other bytes lie in the neighbouring matches, which the level
-    // launches rewrite.
-    const bool words = tiled && j.min_match >= 3;
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
-        if (r[u] && words) {
+        if (r[u] && staged) {
+            const uint32_t a0 = pos - base16, w0 = a0 & ~3u, w1 = (a0 + r[u] + 3) & ~3u;
+            const uint32_t q0 = (uint32_t)((uint64_t)d.lit_at + lq - (a0 - w0) - la);  // staged byte for tile byte w0
+            for (uint32_t o = w0; o < w1; o += 4) {
+                const uint32_t q = q0 + (o - w0);
+                *(uint32_t *)(L.u.tile + o) = __builtin_amdgcn_alignbyte(L.stage[(q >> 2) + 1], L.stage[q >> 2], q & 3);
+            }
+        } else if (r[u] && words) {
             const uint32_t a0 = pos - base16, w0 = a0 & ~3u, w1 = (a0 + r[u] + 3) & ~3u;
             const uint64_t s0 = (uint64_t)d.lit_at + lq - (a0 - w0);  // stream byte that lands on tile byte w0
             for (uint32_t o = w0; o < w1; o += 16) {
