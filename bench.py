@@ -97,13 +97,17 @@ def cpu_baseline(stream, x, budget_s: float = 12.0) -> dict:
             cpu["model"] = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "?")
     except OSError:
         cpu["model"] = "?"
-    mt = res["threads"]
-    return {"value": round(mt["gbps"], 3), "unit": "GB/s", "cores": mt["threads"], "kind": "oracle",
-            "sample": f"whole stream ({n} decoded bytes) decoded {mt['reps']} times by the oracle's "
-                      f"block-parallel decoder; sequential decoder {res['sequential']['gbps']:.3f} GB/s "
-                      f"on 1 core over {res['sequential']['reps']} decodes",
-            "sequential_value": round(res["sequential"]["gbps"], 3), "host_cpu": cpu["model"],
-            "host_threads_visible": len(os.sched_getaffinity(0))}
+    best = max(res, key=lambda k: res[k]["gbps"])
+    b = res[best]
+    return {"value": round(b["gbps"], 3), "unit": "GB/s", "cores": b["threads"], "kind": "oracle",
+            "sample": f"whole stream ({n} decoded bytes), repeated for about {budget_s / 2:.0f} s per decoder; "
+                      f"value is the faster of the oracle's sequential decoder "
+                      f"({res['sequential']['gbps']:.3f} GB/s on 1 thread, {res['sequential']['reps']} decodes) "
+                      f"and its block-parallel decoder ({res['threads']['gbps']:.3f} GB/s on "
+                      f"{res['threads']['threads']} threads, {res['threads']['reps']} decodes)",
+            "sequential_value": round(res["sequential"]["gbps"], 3),
+            "threads_value": round(res["threads"]["gbps"], 3), "threads": res["threads"]["threads"],
+            "host_cpu": cpu["model"], "host_threads_visible": len(os.sched_getaffinity(0))}
 
 
 def base_line(value, steps, warmup, ms):
@@ -398,6 +402,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fastq256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plan", action="store_true", help="plain mode: skip the plan + graph leg")
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "served", "algorithmic"])
     ap.add_argument("--streams", type=int, default=4096, help="batched: descriptors per call")
     ap.add_argument("--distinct", type=int, default=256, help="batched: distinct encoded streams")
@@ -520,7 +525,8 @@ def main():
         "kernel_groups": {k: {"ms_per_launch": round(v["ms_per_launch"], 5), "launches": v["launches"]}
                           for k, v in per_group.items()},
     }
-    line["plan_graph_tuned"] = plan_graph_leg(ds, out, ws, status, stream, x_dev, args)
+    if not args.no_plan:
+        line["plan_graph_tuned"] = plan_graph_leg(ds, out, ws, status, stream, x_dev, args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(s, x)
     print(json.dumps(line), flush=True)

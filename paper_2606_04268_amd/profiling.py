@@ -1,12 +1,15 @@
-"""HBM traffic of the decoder's kernels from rocprofv3 counters.
+"""Kernel timings and HBM traffic of the decoder from rocprofv3 runs.
 
-Two helpers for the counter runs whose summaries sit in ``profiles/``:
+Helpers for the profiler runs whose summaries sit in ``profiles/``:
 
 ``python -m paper_2606_04268_amd.profiling copycal``
     A plain device copy of 1 GiB (three times), run under
     ``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` to calibrate the
     counters: the copy reads and writes exactly 1 GiB, so
     ``1 GiB / counter`` is the factor that turns each counter into bytes.
+
+``python -m paper_2606_04268_amd.profiling trace ...``
+    A Markdown summary of a ``rocprofv3 --kernel-trace --stats`` run.
 
 ``python -m paper_2606_04268_amd.profiling summarize ...``
     Reads the counter CSVs of a decode run and of the copy run and writes a
@@ -145,6 +148,49 @@ def summarize(args):
     print("\n".join(lines))
 
 
+def trace(args):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run: per-kernel
+    statistics, and the kernels of the last decode one by one."""
+    with open(os.path.join(args.dir, "run_kernel_stats.csv")) as f:
+        stats = list(csv.DictReader(f))
+    with open(os.path.join(args.dir, "run_kernel_trace.csv")) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    lines = [f"# Kernel trace: {args.title}", "", f"Workload: {args.workload}", "",
+             "Command (from the repository root):", "", "```"] + args.command + ["```", "",
+             "## Per-kernel statistics over the run", "",
+             "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share of GPU time |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
+    starts = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "k_setup"]
+    if starts:
+        i0 = starts[-1]
+        seq = []
+        for r in rows[i0:]:
+            k = _short(r["Kernel_Name"])
+            if k not in GROUP_OF and k != "k_seal":
+                break
+            seq.append(r)
+        t0 = int(seq[0]["Start_Timestamp"])
+        lines += ["", "## The last decode, kernel by kernel", "",
+                  "Start times are relative to `k_setup`; gaps between kernels include the profiler's own.", "",
+                  "| Kernel | Grid (work-items) | Start (us) | Duration (us) |", "|---|---|---|---|"]
+        lvl = 0
+        for r in seq:
+            k = _short(r["Kernel_Name"])
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            label = k
+            if k == "k_level":
+                label = f"k_level (launch {lvl})"
+                lvl += 1
+            lines.append(f"| {label} | {r['Grid_Size_X']} | {(a - t0) / 1e3:.1f} | {(b - a) / 1e3:.1f} |")
+        total = (int(seq[-1]["End_Timestamp"]) - t0) / 1e3
+        lines += ["", f"First kernel start to last kernel end: {total:.1f} us."]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def load_traffic(path: str):
     """The traffic record of a summary, or None when it is absent or was
     measured on another version of the kernel source."""
@@ -173,9 +219,17 @@ def main():
     s.add_argument("--key", required=True)
     s.add_argument("--command", action="append", default=[])
     s.add_argument("--out", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("--dir", required=True)
+    t.add_argument("--title", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--command", action="append", default=[])
+    t.add_argument("--out", required=True)
     args = ap.parse_args()
     if args.cmd == "copycal":
         copycal()
+    elif args.cmd == "trace":
+        trace(args)
     else:
         summarize(args)
 
