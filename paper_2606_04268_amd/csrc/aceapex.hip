@@ -11,16 +11,18 @@
 //             workgroups also clear each stream's status and level cursors;
 //             for a single stream, workgroup 0 turns the stream's level table
 //             (matches per level) into the record slots of every level.
-//   k_parse   one workgroup per chunk, four sequences per thread.  When every
-//             cmd/len/lvl value of the chunk is one byte long (the slice length
-//             equals the value count) each thread reads its four values with a
-//             single 4-byte load per stream; otherwise three waves decode the
-//             LEB128 slices into LDS first.  A workgroup scan turns run and
-//             match lengths into output and literal offsets.  The literal runs
-//             are placed in an LDS image of the chunk's output span, which is
-//             written with aligned 16-byte stores (Sec. 3.2); every match
-//             becomes a 12-byte record (dst, src, len | stream << 21) in the
-//             slots of its level.
+//   k_parse   one workgroup per chunk, four sequences per thread.  The chunk's
+//             literal bytes are first copied into LDS by direct global-to-LDS
+//             loads.  When every cmd/len/lvl value of the chunk is one byte
+//             long (the slice length equals the value count) each thread reads
+//             its four values with a single 4-byte load per stream; otherwise
+//             three waves decode the LEB128 slices into LDS.  A workgroup scan
+//             turns run and match lengths into output and literal offsets.
+//             The literal runs are placed, as whole aligned words, in an LDS
+//             image of the chunk's output span, which is written with aligned
+//             16-byte stores (Sec. 3.2); every match becomes a 12-byte record
+//             (dst, src, len | stream << 21) in the slots of its level.
+//   k_seal    (batches) record slots a corrupt stream left unfilled get length 0.
 //   k_level   one launch per level k (Sec. 7.1): the copies of level k read
 //             only bytes written by literals or by lower levels and are
 //             independent of each other, so every thread simply runs four
@@ -28,6 +30,11 @@
 //   k_tail    the deep levels that hold few matches run in a single workgroup,
 //             level after level, separated by workgroup barriers: one CU, so
 //             no cache maintenance between levels.
+//
+// k_parse, k_level and k_tail are compiled twice: for one stream, whose
+// output, size and status are kernel arguments, and for batches, where each
+// chunk and record names its stream.  A plan (aceapex_plan_*) lays a batch out
+// once and replays the same launches, optionally as a captured HIP graph.
 //
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
 // their index; k_parse and k_level hand each XCD one contiguous range of
@@ -250,13 +257,14 @@ __device__ __forceinline__ void fetch_records(const Batch &B, uint32_t r0, uint3
 // The stream of each fetched record: its output, size and status.  In a
 // batch every slot of a level was filled in this decode or given length 0 by
 // k_seal, so the stream index carried by the record is all that is needed.
+template <bool BATCH>
 __device__ __forceinline__ void resolve_records(const Batch &B, const uint32_t *lj, uint8_t **ob, uint32_t *on,
                                                 int32_t **sp, uint32_t *len)
 {
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
         len[u] = lj[u] & LEN_MASK;
-        if (!B.jobs) {
+        if (!BATCH) {
             ob[u] = B.one.out;
             on[u] = B.one.n;
             sp[u] = B.one.status;
@@ -277,13 +285,14 @@ __device__ __forceinline__ void resolve_records(const Batch &B, const uint32_t *
 }
 
 // Fetch and resolve ROUND records (see fetch_records, resolve_records).
+template <bool BATCH>
 __device__ __forceinline__ void load_records(const Batch &B, uint32_t r0, uint32_t stride,
                                              uint32_t r_end, uint8_t **ob, uint32_t *on, int32_t **sp,
                                              uint32_t *dst, uint32_t *src, uint32_t *len)
 {
     uint32_t lj[ROUND];
     fetch_records(B, r0, stride, r_end, dst, src, lj);
-    resolve_records(B, lj, ob, on, sp, len);
+    resolve_records<BATCH>(B, lj, ob, on, sp, len);
 }
 
 // ------------------------------------------------------------------- scans
@@ -547,13 +556,14 @@ struct ParseLds {
     uint32_t bad;
 } __attribute__((aligned(16)));
 
+template <bool BATCH>
 __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
 {
     __shared__ ParseLds L;
     const uint32_t t = threadIdx.x, wave = t >> 6;
     const uint32_t g = xcd_slot(blockIdx.x, gridDim.x);  // global chunk
-    const uint32_t sj = B.jobs ? B.chunk_job[g] : 0u;    // its stream
-    const Job &j = job_of(B, sj);
+    const uint32_t sj = BATCH ? B.chunk_job[g] : 0u;     // its stream
+    const Job &j = BATCH ? B.jobs[sj] : B.one;
     const uint32_t c = g - j.c0;
     const uint32_t K = 1u << j.chunk_log2;
     const uint32_t nl = min(j.max_level + 1, LH);
@@ -822,6 +832,7 @@ __global__ void __launch_bounds__(NT) k_seal(Batch B)
 // The level's slots are split into one contiguous part per XCD; the
 // workgroups of an XCD sweep its part together, tile after tile, so that the
 // destinations and sources they touch at one time share its L2.
+template <bool BATCH>
 __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
 {
     uint32_t R0, R1;
@@ -835,7 +846,7 @@ __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
         uint8_t *ob[ROUND];
         int32_t *sp[ROUND];
         uint32_t on[ROUND], dst[ROUND], src[ROUND], len[ROUND];
-        load_records(B, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
+        load_records<BATCH>(B, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
         run_records(ob, on, sp, dst, src, len, B.long_copy);
     }
 }
@@ -844,6 +855,7 @@ __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
 // threads.  The first round of the next level's records is fetched before the
 // current level's copies, so that after each barrier only the source reads
 // remain.
+template <bool BATCH>
 __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
 {
     uint32_t nd[ROUND], nsr[ROUND], nlj[ROUND];
@@ -863,11 +875,11 @@ __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
         uint8_t *ob[ROUND];
         int32_t *sp[ROUND];
         uint32_t on[ROUND], len[ROUND];
-        resolve_records(B, lj, ob, on, sp, len);
+        resolve_records<BATCH>(B, lj, ob, on, sp, len);
         run_records(ob, on, sp, dst, src, len, B.long_copy);
         for (uint32_t r = lo_k + ROUND * NT_TAIL + threadIdx.x;; r += ROUND * NT_TAIL) {
             if (__ballot(r < hi_k) == 0) break;
-            load_records(B, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
+            load_records<BATCH>(B, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
             run_records(ob, on, sp, dst, src, len, B.long_copy);
         }
         __syncthreads();
@@ -994,9 +1006,17 @@ void launch_levels(const Batch &B, const uint64_t *counts, uint64_t n_seq, const
     for (uint32_t k = 0; k < tail; k++) {
         const uint64_t cnt = counts ? counts[k] : n_seq;
         if (counts && !cnt) continue;
-        hipLaunchKernelGGL(k_level, dim3(level_wgs(cnt, tn)), dim3(NT), 0, st, B, k);
+        if (B.jobs)
+            hipLaunchKernelGGL(k_level<true>, dim3(level_wgs(cnt, tn)), dim3(NT), 0, st, B, k);
+        else
+            hipLaunchKernelGGL(k_level<false>, dim3(level_wgs(cnt, tn)), dim3(NT), 0, st, B, k);
     }
-    if (tail <= B.max_level) hipLaunchKernelGGL(k_tail, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
+    if (tail <= B.max_level) {
+        if (B.jobs)
+            hipLaunchKernelGGL(k_tail<true>, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
+        else
+            hipLaunchKernelGGL(k_tail<false>, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
+    }
 }
 
 // ---- one stream
@@ -1074,7 +1094,7 @@ int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     if (in.n_blocks) {
         {
             PhaseScope ps(PH_PARSE, st);
-            hipLaunchKernelGGL(k_parse, dim3(in.n_chunks), dim3(NT), 0, st, B);
+            hipLaunchKernelGGL(k_parse<false>, dim3(in.n_chunks), dim3(NT), 0, st, B);
         }
         if (in.n_seq) {
             std::vector<uint64_t> cnt;
@@ -1236,7 +1256,7 @@ void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
     }
     if (g.n_chunks) {
         PhaseScope ps(PH_PARSE, st, timed);
-        hipLaunchKernelGGL(k_parse, dim3((uint32_t)g.n_chunks), dim3(NT), 0, st, B);
+        hipLaunchKernelGGL(k_parse<true>, dim3((uint32_t)g.n_chunks), dim3(NT), 0, st, B);
     }
     if (g.n_seq) {
         {
