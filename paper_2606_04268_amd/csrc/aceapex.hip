@@ -66,7 +66,7 @@ constexpr uint32_t JOBS_MAX = 1u << (32 - LEN_BITS);  // streams per launch sequ
 constexpr uint32_t ROUND = 4;               // records per thread per round of k_level / k_tail
 // Default schedule (each value can be changed per plan, see aceapex_tuning):
 constexpr uint32_t LONG_COPY = 128;         // matches longer than this are copied by a whole wave
-constexpr uint32_t LEVEL_WG_MAX = 2048;     // workgroups of one level launch, at most
+constexpr uint32_t LEVEL_WG_MAX = 512;      // workgroups of one level launch, at most
 constexpr uint32_t TAIL_LEVEL_MAX = 8192;   // levels with at most this many matches may join the tail
 constexpr uint32_t XCD_PARTS = 8;           // contiguous parts of a level's records, one per XCD
 constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
@@ -1066,11 +1066,22 @@ Job make_job(const aceapex_stream &s, void *d_out, int32_t *status, ChunkDesc *c
     return j;
 }
 
-int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st)
+// One launch sequence: one stream (single, kernel arguments name it) or a
+// batch (each chunk and record names its stream), with the level counts the
+// host schedule needs.
+struct Group {
+    Batch B;
+    std::vector<uint64_t> tot;  // matches per level, or empty when unknown (one launch per level)
+    uint64_t n_blocks = 0, n_chunks = 0, n_seq = 0;
+    uint32_t n = 0;
+    bool single = false;
+};
+
+void build_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, Group &g)
 {
     const aceapex_info &in = s.info;
     const WsLayout w = ws_single(in);
-    Batch B;
+    Batch &B = g.B;
     memset(&B, 0, sizeof B);
     B.one = make_job(s, d_out, d_status ? d_status : (int32_t *)(ws + w.status), (ChunkDesc *)(ws + w.chunks),
                      ws + w.blk_ok, 0, 0, 0);
@@ -1083,28 +1094,13 @@ int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     B.n_chunks = in.n_chunks;
     B.max_level = in.max_level;
     B.n_seq = in.n_seq;
-    const Tune tn;
-    B.long_copy = tn.long_copy;
-    B.xcd_parts = tn.xcd_parts;
-    {
-        PhaseScope ps(PH_SETUP, st);
-        hipLaunchKernelGGL(k_setup, dim3(std::max<uint32_t>(1, std::min<uint32_t>(in.n_blocks, 65535))), dim3(NT), 0,
-                           st, B);
-    }
-    if (in.n_blocks) {
-        {
-            PhaseScope ps(PH_PARSE, st);
-            hipLaunchKernelGGL(k_parse<false>, dim3(in.n_chunks), dim3(NT), 0, st, B);
-        }
-        if (in.n_seq) {
-            std::vector<uint64_t> cnt;
-            if (s.h_levels) cnt.assign(s.h_levels, s.h_levels + in.max_level + 1);
-            launch_levels(B, s.h_levels ? cnt.data() : nullptr, in.n_seq, tn, st, true);
-        }
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e);
-    return ACEAPEX_OK;
+    g.tot.clear();
+    if (s.h_levels) g.tot.assign(s.h_levels, s.h_levels + in.max_level + 1);
+    g.n_blocks = in.n_blocks;
+    g.n_chunks = in.n_chunks;
+    g.n_seq = in.n_seq;
+    g.n = 1;
+    g.single = true;
 }
 
 // ---- a batch of streams (all with host level tables), at most JOBS_MAX
@@ -1177,12 +1173,6 @@ int stage_buffer(size_t bytes, Staging *&out)
 
 // One launch sequence of a batch: the kernel arguments and the level counts
 // the host schedule needs.
-struct Group {
-    Batch B;
-    std::vector<uint64_t> tot;  // matches per level over the group
-    uint64_t n_blocks = 0, n_chunks = 0, n_seq = 0;
-    uint32_t n = 0;
-};
 
 // Lay out the group d[0, n) in the workspace ws: the host tables (stream
 // table, per-(stream, level) slot ranges, per-level slot offsets) are written
@@ -1248,6 +1238,22 @@ void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
     Batch B = g.B;
     B.long_copy = tn.long_copy;
     B.xcd_parts = tn.xcd_parts;
+    const uint64_t *counts = g.tot.empty() ? nullptr : g.tot.data();
+    if (g.single) {
+        {
+            PhaseScope ps(PH_SETUP, st, timed);
+            hipLaunchKernelGGL(k_setup, dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g.n_blocks, 65535))),
+                               dim3(NT), 0, st, B);
+        }
+        if (g.n_blocks) {
+            {
+                PhaseScope ps(PH_PARSE, st, timed);
+                hipLaunchKernelGGL(k_parse<false>, dim3((uint32_t)g.n_chunks), dim3(NT), 0, st, B);
+            }
+            if (g.n_seq) launch_levels(B, counts, g.n_seq, tn, st, timed);
+        }
+        return;
+    }
     {
         PhaseScope ps(PH_SETUP, st, timed);
         hipLaunchKernelGGL(k_map, dim3(g.n), dim3(NT), 0, st, B);
@@ -1263,8 +1269,18 @@ void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
             PhaseScope ps(PH_PARSE, st, timed);
             hipLaunchKernelGGL(k_seal, dim3(g.n), dim3(NT), 0, st, B);
         }
-        launch_levels(B, g.tot.data(), g.n_seq, tn, st, timed);
+        launch_levels(B, counts, g.n_seq, tn, st, timed);
     }
+}
+
+int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st)
+{
+    Group g;
+    build_single(s, d_out, ws, d_status, g);
+    enqueue_group(g, Tune(), st, true);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+    return ACEAPEX_OK;
 }
 
 int launch_batch(const aceapex_desc *d, uint32_t n, uint8_t *ws, hipStream_t st)
@@ -1514,6 +1530,13 @@ int aceapex_plan_create(const aceapex_desc *h_descs, uint32_t n, void *d_workspa
     }
     hipStream_t st = (hipStream_t)hip_stream;
     uint8_t *ws = (uint8_t *)d_workspace;
+    if (n == 1) {  // one stream: the single-stream kernels, nothing staged
+        Group g;
+        build_single(h_descs[0].s, h_descs[0].d_out, ws, h_descs[0].d_status, g);
+        p->groups.push_back(std::move(g));
+        *plan = (aceapex_plan *)p;
+        return ACEAPEX_OK;
+    }
     std::vector<uint8_t> h;
     for (uint32_t i = 0, m; i < n; i += m) {
         m = group_size(h_descs + i, n - i);
