@@ -438,7 +438,7 @@ def main():
     x = synth.make(wl["kind"], wl["size"], wl["seed"])
     log(f"generated {wl['kind']} {x.size} bytes in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    s = ax.encode(x, **wl["enc"])
+    s = ax.encode(x, verbose=1 if wl["enc"].get("max_depth") else 0, **wl["enc"])
     log(f"encoded to {s.size} bytes in {time.perf_counter() - t0:.1f}s")
     st = stream_stats(s)
     log(f"stream: {st['n_seq']} matches, {st['n_deep']} at level >= 1, max level {st['max_level']}, "

@@ -257,6 +257,8 @@ typedef struct {
     uint32_t tiebreak;    /* among candidates of equal length: 0 lowest level, 1 most recent      */
     uint32_t chunk_log2;  /* sequences per chunk-index entry (10)                                 */
     uint32_t threads;     /* host threads, 0 = all                                                */
+    uint32_t verbose;     /* nonzero: the sequential depth-limited parse reports its progress on  */
+                          /* stderr every 64 blocks                                               */
 } aceapex_enc_opts;
 
 /* Fill *o with the defaults above.  Pure host code. */

@@ -36,7 +36,7 @@ def encode(data, *, with_hash: bool = True, **opts) -> np.ndarray:
     """Encode host bytes into a stream (host encoder in libaceapex.so).
 
     Options (see aceapex_enc_opts): block_log2, min_match, flatten, max_depth,
-    chain_depth, hash_bits, tiebreak, chunk_log2, threads.
+    chain_depth, hash_bits, tiebreak, chunk_log2, threads, verbose.
     """
     o = _abi.enc_defaults()
     for k, v in opts.items():

@@ -47,7 +47,7 @@ class EncOpts(ctypes.Structure):
     """aceapex_enc_opts."""
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "block_log2", "min_match", "flatten", "max_depth", "chain_depth", "hash_bits",
-        "tiebreak", "chunk_log2", "threads")]
+        "tiebreak", "chunk_log2", "threads", "verbose")]
 
 
 class Tuning(ctypes.Structure):

@@ -22,6 +22,7 @@
 // With a depth limit the candidate lengths depend on levels, and the parse
 // runs block after block on one thread.
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -406,6 +407,9 @@ int64_t Encoder::run(uint8_t **result)
         for (uint64_t b = 0; b < nb_; b++) {
             parse_limited(b);
             if (o_.flatten) { flatten(b); relevel(b); }
+            if (o_.verbose && (b + 1) % 64 == 0)
+                fprintf(stderr, "aceapex_encode: depth-limited parse, %llu of %llu blocks\n",
+                        (unsigned long long)(b + 1), (unsigned long long)nb_);
         }
     }
     std::vector<uint32_t>().swap(link_);
@@ -500,6 +504,7 @@ void aceapex_enc_defaults(aceapex_enc_opts *o)
     o->tiebreak = 0;
     o->chunk_log2 = 10;
     o->threads = 0;
+    o->verbose = 0;
 }
 
 int64_t aceapex_encode(const void *h_in, uint64_t n, const aceapex_enc_opts *opts, void **h_stream)
