@@ -57,7 +57,6 @@ constexpr int NT_TAIL = 1024;               // threads of the tail workgroup
 constexpr uint32_t K_LOG2_MAX = 10;         // sequences per chunk, at most
 constexpr uint32_t K_MAX = 1u << K_LOG2_MAX;
 constexpr uint32_t PER = K_MAX / NT;        // sequences per thread in k_parse
-constexpr uint32_t LH = 256;                // levels bucketed through LDS; deeper ones use global atomics
 constexpr uint32_t HDR = 64, BLKHDR = 32, CHUNK_ENT = 32;
 constexpr uint32_t BLOCK_LOG2_MAX = 20;
 constexpr uint32_t LEN_BITS = 21;           // a match length needs 21 bits (blocks of at most 2^20 bytes)
@@ -70,7 +69,6 @@ constexpr uint32_t LEVEL_WG_MAX = 512;      // workgroups of one level launch, a
 constexpr uint32_t TAIL_LEVEL_MAX = 8192;   // levels with at most this many matches may join the tail
 constexpr uint32_t XCD_PARTS = 8;           // contiguous parts of a level's records, one per XCD
 constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
-constexpr uint32_t STAGE_BYTES = 7680;      // a chunk's literals staged in LDS by k_parse, at most
 constexpr uint64_t CHUNKS_MAX = 1ull << 24;  // chunks of one launch sequence (the k_parse grid), at most
 
 typedef uint16_t u16u __attribute__((aligned(1)));
@@ -540,6 +538,11 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
 
 // --------------------------------------------------------------- k_parse
 
+// k_parse comes in three LDS shapes, picked by the deepest level of the
+// launch: LH levels are ranked in LDS (deeper ones take one global atomic per
+// match), and up to STAGE bytes of a chunk's literals are staged in LDS.  Each
+// shape keeps six workgroups per CU.
+template <uint32_t LH, uint32_t STAGE>
 struct ParseLds {
     union {
         struct {
@@ -549,17 +552,17 @@ struct ParseLds {
         } v;
         uint8_t tile[TILE_BYTES];      // after the scan: the chunk's output span, literals in place
     } u;
-    uint32_t stage[STAGE_BYTES / 4 + 4];  // the chunk's literal bytes from a 16-byte boundary
+    uint32_t stage[STAGE / 4 + 4];  // the chunk's literal bytes from a 16-byte boundary
     uint32_t lcount[LH];         // matches of the chunk per level (levels < LH)
     uint32_t lbase[LH];          // record slot reserved for them
     uint64_t tmp[NT / 64];
     uint32_t bad;
 } __attribute__((aligned(16)));
 
-template <bool BATCH>
+template <bool BATCH, uint32_t LH, uint32_t STAGE>
 __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
 {
-    __shared__ ParseLds L;
+    __shared__ ParseLds<LH, STAGE> L;
     const uint32_t t = threadIdx.x, wave = t >> 6;
     const uint32_t g = xcd_slot(blockIdx.x, gridDim.x);  // global chunk
     const uint32_t sj = BATCH ? B.chunk_job[g] : 0u;     // its stream
@@ -603,7 +606,7 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
     const bool words = tiled && j.min_match >= 3;
     const uint64_t la = ((uint64_t)d.lit_at - 4) & ~(uint64_t)15;
     const uint64_t lend = ((uint64_t)d.lit_at + d.lit_n + 15) & ~(uint64_t)15;
-    const bool staged = words && d.lit_at >= 4 && lend - la <= STAGE_BYTES && lend <= j.comp_bytes;
+    const bool staged = STAGE && words && d.lit_at >= 4 && lend - la <= STAGE && lend <= j.comp_bytes;
     if (staged) {
         const uint32_t nblk = (uint32_t)((lend - la) >> 4);
         for (uint32_t b0 = 64 * wave; b0 < nblk; b0 += NT) {  // b0: the wave's first 16-byte block
@@ -807,6 +810,18 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
         rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u] | tag;
     }
     if (bad) fail(j, ACEAPEX_E_CORRUPT);
+}
+
+// The k_parse shape for a launch whose deepest level is max_level.
+template <bool BATCH>
+void launch_parse(const Batch &B, uint32_t grid, hipStream_t st)
+{
+    if (B.max_level < 256)
+        hipLaunchKernelGGL((k_parse<BATCH, 256, 7680>), dim3(grid), dim3(NT), 0, st, B);
+    else if (B.max_level < 1024)
+        hipLaunchKernelGGL((k_parse<BATCH, 1024, 1536>), dim3(grid), dim3(NT), 0, st, B);
+    else
+        hipLaunchKernelGGL((k_parse<BATCH, 4096, 0>), dim3(grid), dim3(NT), 0, st, B);
 }
 
 // --------------------------------------------------------------- k_seal
@@ -1248,7 +1263,7 @@ void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
         if (g.n_blocks) {
             {
                 PhaseScope ps(PH_PARSE, st, timed);
-                hipLaunchKernelGGL(k_parse<false>, dim3((uint32_t)g.n_chunks), dim3(NT), 0, st, B);
+                launch_parse<false>(B, (uint32_t)g.n_chunks, st);
             }
             if (g.n_seq) launch_levels(B, counts, g.n_seq, tn, st, timed);
         }
@@ -1262,7 +1277,7 @@ void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
     }
     if (g.n_chunks) {
         PhaseScope ps(PH_PARSE, st, timed);
-        hipLaunchKernelGGL(k_parse<true>, dim3((uint32_t)g.n_chunks), dim3(NT), 0, st, B);
+        launch_parse<true>(B, (uint32_t)g.n_chunks, st);
     }
     if (g.n_seq) {
         {

@@ -115,15 +115,16 @@ def test_doubling_string_long_matches():
     parity(np.frombuffer(x, np.uint8), s, "doubling")
 
 
-def test_level_chain_beyond_lds_histogram():
-    """2000 chained 4-byte copies: levels 0..1999, past the per-workgroup
-    level histogram, so the deep levels take the global-atomic path."""
-    m = 2000
+@pytest.mark.parametrize("m", [500, 2000, 5000])
+def test_level_chains_of_every_histogram_shape(m):
+    """m chained 4-byte copies: levels 0..m-1.  500 and 2000 levels take the
+    parse shapes with 1024- and 4096-level LDS histograms; 5000 levels go past
+    the largest, so the deepest levels take one global atomic per match."""
     blocks = [([(4, 4, 0)] + [(0, 4, 4 * i) for i in range(1, m)], 0)]
     n = 4 + 4 * m
-    s, want = streamgen.build(blocks, b"abcd", n, block_log2=14, chunk_log2=5)
+    s, want = streamgen.build(blocks, b"abcd", n, block_log2=16, chunk_log2=5)
     assert oracle.header_fields(s)["max_level"] == m - 1
-    parity(np.frombuffer(want, np.uint8), s, "chain2000")
+    parity(np.frombuffer(want, np.uint8), s, f"chain{m}")
 
 
 def test_edge_cases():
