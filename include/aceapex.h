@@ -204,12 +204,6 @@ typedef struct {
                              /* together in one workgroup (default 8192; 0 = one launch per level)   */
     uint32_t long_copy;      /* matches longer than this are copied by a whole wave (16..2^21; 128)  */
     uint32_t xcd_parts;      /* contiguous parts of a level's matches, one per XCD (1..8; default 8) */
-    uint32_t xcd_tail;       /* 1: the tail runs on the CUs of one XCD, whose shared L2 lets its     */
-                             /* workgroups pass levels with an XCD-local barrier; 0 (default): in   */
-                             /* one workgroup.  With 1, the launch expects the CUs of an XCD to     */
-                             /* itself: launches of plans with xcd_tail = 1 must not overlap other  */
-                             /* such launches on other streams (a wait that cannot finish gives up  */
-                             /* after a few seconds with ACEAPEX_E_TIMEOUT)                         */
 } aceapex_tuning;
 
 /* The default schedule (the one aceapex_decode and aceapex_decode_many use). */
@@ -236,12 +230,11 @@ int aceapex_plan_set_tuning(aceapex_plan *plan, const aceapex_tuning *tuning);
 int aceapex_plan_get_tuning(const aceapex_plan *plan, aceapex_tuning *tuning);
 
 /* Autotune the schedule on this plan's own streams: coordinate descent over
- * xcd_tail, level_wg_max, tail_level_max, long_copy and xcd_parts, each
- * candidate timed with HIP events over reps launches after one warm-up; a
- * candidate is kept when it is at least 1% faster.  The plan keeps the
- * winner, also written to *best when best is not NULL.  Synchronous; runs
- * about 18 * (reps + 1) decodes of the batch, each leaving the outputs
- * decoded.  (It may pick xcd_tail = 1: see aceapex_tuning.) */
+ * level_wg_max, tail_level_max, long_copy and xcd_parts, each candidate timed
+ * with HIP events over reps launches after one warm-up; a candidate is kept
+ * when it is at least 1% faster.  The plan keeps the winner, also written to
+ * *best when best is not NULL.  Synchronous; runs about 15 * (reps + 1)
+ * decodes of the batch, each leaving the outputs decoded. */
 int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceapex_tuning *best);
 
 /* Free the plan (NULL is ignored).  Call it once no launch is in flight. */

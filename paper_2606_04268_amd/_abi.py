@@ -52,8 +52,7 @@ class EncOpts(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """aceapex_tuning."""
-    _fields_ = [(n, ctypes.c_uint32) for n in ("level_wg_max", "tail_level_max", "long_copy", "xcd_parts",
-                                               "xcd_tail")]
+    _fields_ = [(n, ctypes.c_uint32) for n in ("level_wg_max", "tail_level_max", "long_copy", "xcd_parts")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

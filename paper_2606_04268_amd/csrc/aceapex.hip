@@ -54,8 +54,6 @@ namespace {
 
 constexpr int NT = 256;                     // threads per workgroup
 constexpr int NT_TAIL = 1024;               // threads of the tail workgroup
-constexpr uint32_t XT_GROUPS = 256;         // k_xtail workgroups (NT_TAIL threads each): 32 per XCD
-constexpr uint32_t XT_SPIN_MAX = 1u << 22;  // k_xtail: polls of a wait before it gives up (E_TIMEOUT)
 constexpr uint32_t K_LOG2_MAX = 10;         // sequences per chunk, at most
 constexpr uint32_t K_MAX = 1u << K_LOG2_MAX;
 constexpr uint32_t PER = K_MAX / NT;        // sequences per thread in k_parse
@@ -117,7 +115,6 @@ struct Batch {
     uint32_t n_seq;             // matches over the batch
     uint32_t long_copy;         // matches longer than this are copied by a whole wave
     uint32_t xcd_parts;         // k_level: contiguous parts of a level's records (1..8)
-    uint32_t *sync;             // k_xtail: chosen XCD + 1, check-ins, participants, arrivals, abort
 };
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
@@ -438,7 +435,6 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
     __shared__ uint64_t tmp[NT / 64];
     const uint32_t t = threadIdx.x;
 
-    if (blockIdx.x == 0 && t < 8) B.sync[t] = 0;
     if (!B.jobs && blockIdx.x == 0) {
         // single stream: its level table -> record slots of every level
         const Job &j = B.one;
@@ -905,91 +901,6 @@ __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
     }
 }
 
-// The deep levels [k0, max_level] on the CUs of one XCD.  The workgroups of
-// an XCD share its L2, so the copies of one level reach the next level's
-// reads through that L2: between levels the participating workgroups drain
-// their stores, meet at a counter (device-scope atomics) and drop their CU's
-// L1 -- no L2 write-back, unlike a barrier across XCDs.  Participants are the
-// workgroups that run on the XCD of the first workgroup to start, as read
-// from the hardware XCC_ID register; the others check in and leave.  Every
-// wait is bounded: a workgroup that gives up marks the decode E_TIMEOUT, and
-// all participants then leave.
-constexpr uint32_t XT_NONE = 0xffffffffu;
-
-__device__ __forceinline__ bool xt_wait(uint32_t *word, uint32_t target, uint32_t *abort)
-{
-    for (uint32_t spins = 0; __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; spins++) {
-        if (spins >= XT_SPIN_MAX || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return true;
-}
-
-template <bool BATCH>
-__device__ void xt_timeout(const Batch &B)
-{
-    if (!BATCH) {
-        fail(B.one, ACEAPEX_E_TIMEOUT);
-    } else {
-        for (uint32_t i = 0; i < B.n_jobs; i++) fail(B.jobs[i], ACEAPEX_E_TIMEOUT);
-    }
-}
-
-template <bool BATCH>
-__global__ void __launch_bounds__(NT_TAIL) k_xtail(Batch B, uint32_t k0)
-{
-    __shared__ uint32_t s_part, s_np, s_ok;
-    uint32_t *const sync = B.sync;  // [0] XCD + 1, [1] check-ins, [2] participants, [3] arrivals, [4] abort
-    const uint32_t t = threadIdx.x;
-    if (t == 0) {
-        const uint32_t xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));  // HW_REG_XCC_ID
-        uint32_t unset = 0;
-        __hip_atomic_compare_exchange_strong(&sync[0], &unset, xcc + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = __hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - 1;
-        uint32_t part = XT_NONE;
-        if (xcc == target) part = __hip_atomic_fetch_add(&sync[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_ok = 1;
-        s_np = 0;
-        if (part != XT_NONE) {  // once every workgroup has checked in, the participant count is final
-            s_ok = xt_wait(&sync[1], gridDim.x, &sync[4]);
-            s_np = __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (!s_ok) xt_timeout<BATCH>(B);
-        }
-        s_part = part;
-    }
-    __syncthreads();
-    const uint32_t p = s_part, np = s_np;
-    if (p == XT_NONE || !s_ok) return;
-    for (uint32_t k = k0; k <= B.max_level; k++) {
-        uint32_t lo, hi;
-        level_range(B, k, lo, hi);
-        for (uint32_t r0 = lo + p * (NT_TAIL * ROUND) + t;; r0 += np * (NT_TAIL * ROUND)) {
-            if (__ballot(r0 < hi) == 0) break;
-            uint8_t *ob[ROUND];
-            int32_t *sp[ROUND];
-            uint32_t on[ROUND], dst[ROUND], src[ROUND], len[ROUND];
-            load_records<BATCH>(B, min(r0, hi - 1), NT_TAIL, r0 < hi ? hi : 0, ob, on, sp, dst, src, len);
-            run_records(ob, on, sp, dst, src, len, B.long_copy);
-        }
-        if (k == B.max_level) break;
-        __builtin_amdgcn_s_waitcnt(0);  // this thread's copies have reached the L2
-        __syncthreads();
-        if (t == 0) {
-            __hip_atomic_fetch_add(&sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_ok = xt_wait(&sync[3], (k - k0 + 1) * np, &sync[4]);
-            if (!s_ok) xt_timeout<BATCH>(B);
-        }
-        __syncthreads();
-        if (!s_ok) return;
-        asm volatile("buffer_inv sc0" ::: "memory");  // this CU's L1 may hold lines the level just rewrote
-    }
-}
-
 // ----------------------------------------------------------------- host side
 
 thread_local int g_last_hip = 0;
@@ -1081,13 +992,12 @@ int hip_fail(hipError_t e)
 struct Tune {
     uint32_t level_wg_max = LEVEL_WG_MAX, tail_level_max = TAIL_LEVEL_MAX;
     uint32_t long_copy = LONG_COPY, xcd_parts = XCD_PARTS;
-    uint32_t xcd_tail = 0;  // 1: the tail runs on the CUs of one XCD (k_xtail); 0: in one workgroup (k_tail)
 };
 
 bool tune_valid(const Tune &t)
 {
     return t.level_wg_max >= 1 && t.level_wg_max <= 65535 && t.long_copy >= 16 && t.long_copy <= (1u << 21) &&
-           t.xcd_parts >= 1 && t.xcd_parts <= 8 && t.xcd_tail <= 1;
+           t.xcd_parts >= 1 && t.xcd_parts <= 8;
 }
 
 uint32_t level_wgs(uint64_t records, const Tune &tn)
@@ -1117,17 +1027,10 @@ void launch_levels(const Batch &B, const uint64_t *counts, uint64_t n_seq, const
             hipLaunchKernelGGL(k_level<false>, dim3(level_wgs(cnt, tn)), dim3(NT), 0, st, B, k);
     }
     if (tail <= B.max_level) {
-        if (tn.xcd_tail) {
-            if (B.jobs)
-                hipLaunchKernelGGL(k_xtail<true>, dim3(XT_GROUPS), dim3(NT_TAIL), 0, st, B, tail);
-            else
-                hipLaunchKernelGGL(k_xtail<false>, dim3(XT_GROUPS), dim3(NT_TAIL), 0, st, B, tail);
-        } else {
-            if (B.jobs)
-                hipLaunchKernelGGL(k_tail<true>, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
-            else
-                hipLaunchKernelGGL(k_tail<false>, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
-        }
+        if (B.jobs)
+            hipLaunchKernelGGL(k_tail<true>, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
+        else
+            hipLaunchKernelGGL(k_tail<false>, dim3(1), dim3(NT_TAIL), 0, st, B, tail);
     }
 }
 
@@ -1201,7 +1104,6 @@ void build_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     B.rec_hi = (uint32_t *)(ws + w.rec_hi);
     B.cursor = (uint32_t *)(ws + w.cursor);
     B.recs = (uint32_t *)(ws + w.recs);
-    B.sync = (uint32_t *)(ws + w.status + 64);  // the status area holds the tail's counters too
     B.n_jobs = 1;
     B.n_blocks = in.n_blocks;
     B.n_chunks = in.n_chunks;
@@ -1220,7 +1122,7 @@ void build_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
 
 struct BatchLayout {
     size_t jobs, rec_lo, rec_hi, level_lo, staged;  // staged = bytes copied from the host
-    size_t cursor, blk_job, chunk_job, chunks, blk_ok, status, sync, recs, total;
+    size_t cursor, blk_job, chunk_job, chunks, blk_ok, status, recs, total;
     uint64_t n_lv, n_blocks, n_chunks, n_seq;
     uint32_t max_level;
 };
@@ -1250,7 +1152,6 @@ BatchLayout ws_batch(const aceapex_desc *d, uint32_t n)
     w.chunks = o; o = align256(o + sizeof(ChunkDesc) * w.n_chunks);
     w.blk_ok = o; o = align256(o + w.n_blocks);
     w.status = o; o = align256(o + 4 * (size_t)n);
-    w.sync = o; o += 256;
     w.recs = o; o = align256(o + 12 * w.n_seq);
     w.total = o;
     return w;
@@ -1334,7 +1235,6 @@ void build_group(const aceapex_desc *d, uint32_t n, uint8_t *ws, uint8_t *h, Gro
     B.cursor = (uint32_t *)(ws + w.cursor);
     B.level_lo = (const uint32_t *)(ws + w.level_lo);
     B.recs = (uint32_t *)(ws + w.recs);
-    B.sync = (uint32_t *)(ws + w.sync);
     B.n_jobs = n;
     B.n_blocks = (uint32_t)w.n_blocks;
     B.n_chunks = (uint32_t)w.n_chunks;
@@ -1483,7 +1383,6 @@ Tune tune_from(const aceapex_tuning &t)
     tn.tail_level_max = t.tail_level_max;
     tn.long_copy = t.long_copy;
     tn.xcd_parts = t.xcd_parts;
-    tn.xcd_tail = t.xcd_tail;
     return tn;
 }
 
@@ -1493,7 +1392,6 @@ void tune_to(const Tune &tn, aceapex_tuning *t)
     t->tail_level_max = tn.tail_level_max;
     t->long_copy = tn.long_copy;
     t->xcd_parts = tn.xcd_parts;
-    t->xcd_tail = tn.xcd_tail;
 }
 
 int enqueue_plan(const PlanImpl *p, const Tune &tn, hipStream_t st, bool timed)
@@ -1759,10 +1657,9 @@ int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceap
     };
     // coordinate descent over the knobs, one at a time, from the current schedule
     static const uint32_t wg[] = {512, 1024, 2048, 4096, 8192};
-    static const uint32_t tail[] = {0, 2048, 8192, 32768, 131072};
+    static const uint32_t tail[] = {0, 2048, 8192, 32768};
     static const uint32_t longc[] = {32, 64, 128, 512};
     static const uint32_t parts[] = {1, 8};
-    static const uint32_t xtail[] = {0, 1};
     Tune cur = p->tune;
     float best_ms = 0.f;
     int rc = timed_run(cur, best_ms);
@@ -1779,7 +1676,6 @@ int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceap
             }
         }
     };
-    sweep(&Tune::xcd_tail, xtail, sizeof xtail / sizeof xtail[0]);
     sweep(&Tune::level_wg_max, wg, sizeof wg / sizeof wg[0]);
     sweep(&Tune::tail_level_max, tail, sizeof tail / sizeof tail[0]);
     sweep(&Tune::long_copy, longc, sizeof longc / sizeof longc[0]);

@@ -109,7 +109,7 @@ def test_plan_argument_errors_need_no_gpu():
     info = _abi.probe(s)
     levels = _abi.level_table(s, info)
     t = _abi.tuning_defaults()
-    assert (t.level_wg_max, t.tail_level_max, t.long_copy, t.xcd_parts, t.xcd_tail) == (512, 8192, 128, 8, 0)
+    assert (t.level_wg_max, t.tail_level_max, t.long_copy, t.xcd_parts) == (512, 8192, 128, 8)
     lib = _abi.load()
     h = ctypes.c_void_p()
     with_table = _abi.Desc(_abi.Stream(16, info, levels), 4096, info.decoded_bytes, 0)
@@ -119,8 +119,7 @@ def test_plan_argument_errors_need_no_gpu():
     assert lib.aceapex_plan_create(arr, 1, 4096, ws, None, None, None) == _abi.E_INVAL  # no plan pointer
     assert lib.aceapex_plan_create((_abi.Desc * 1)(without), 1, 4096, ws, None, None, ctypes.byref(h)) == _abi.E_INVAL
     assert lib.aceapex_plan_create(arr, 1, 4096, ws - 256, None, None, ctypes.byref(h)) == _abi.E_WORKSPACE
-    for k, v in [("level_wg_max", 0), ("level_wg_max", 65536), ("long_copy", 8), ("xcd_parts", 0), ("xcd_parts", 9),
-                 ("xcd_tail", 2)]:
+    for k, v in [("level_wg_max", 0), ("level_wg_max", 65536), ("long_copy", 8), ("xcd_parts", 0), ("xcd_parts", 9)]:
         bad = _abi.tuning_defaults()
         setattr(bad, k, v)
         assert lib.aceapex_plan_create(arr, 1, 4096, ws, ctypes.byref(bad), None, ctypes.byref(h)) == _abi.E_INVAL, k

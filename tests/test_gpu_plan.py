@@ -69,9 +69,7 @@ def test_plan_launch_eager_and_graph(batch):
 
 @pytest.mark.parametrize("knobs", [dict(xcd_parts=1), dict(long_copy=16), dict(long_copy=1 << 21),
                                    dict(tail_level_max=0), dict(tail_level_max=1 << 20),
-                                   dict(level_wg_max=1), dict(level_wg_max=65535),
-                                   dict(xcd_tail=1), dict(xcd_tail=1, tail_level_max=1 << 20),
-                                   dict(xcd_tail=1, tail_level_max=1 << 30, level_wg_max=7)],
+                                   dict(level_wg_max=1), dict(level_wg_max=65535)],
                          ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()))
 def test_every_schedule_decodes_the_same(batch, knobs):
     import paper_2606_04268_amd as ax
@@ -112,30 +110,3 @@ def test_autotune_and_cache(batch, tmp_path):
         assert again.tuning == best
     finally:
         again.close()
-
-
-@pytest.mark.parametrize("m", [600, 5000])
-def test_xcd_tail_runs_long_chains(m):
-    """A chain of m dependent 4-byte copies (levels 0..m-1) with every level in
-    the XCD tail: m - 1 barriers between levels, each checked by the result."""
-    import torch
-
-    import paper_2606_04268_amd as ax
-    import streamgen
-
-    blocks = [([(4, 4, 0)] + [(0, 4, 4 * i) for i in range(1, m)], 0)]
-    n = 4 + 4 * m
-    s, want = streamgen.build(blocks, b"abcd", n, block_log2=16, chunk_log2=5)
-    ds = ax.to_device(s)
-    out = torch.full((n,), POISON, dtype=torch.uint8, device="cuda")
-    plan = ax.Plan([ds], outs=[out], tuning=dict(xcd_tail=1, tail_level_max=1 << 30))
-    try:
-        for graph in (False, True, True):
-            out.fill_(POISON)
-            say(f"[gpu] xcd tail chain {m} graph={graph}")
-            plan.launch(graph=graph)
-            torch.cuda.synchronize()
-            ax.check_status(plan.statuses)
-            assert np.array_equal(out.cpu().numpy(), np.frombuffer(want, np.uint8))
-    finally:
-        plan.close()
