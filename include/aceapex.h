@@ -201,7 +201,7 @@ typedef struct aceapex_plan aceapex_plan;
 typedef struct {
     uint32_t level_wg_max;   /* workgroups of one level launch, at most (1..65535; default 512)     */
     uint32_t tail_level_max; /* the deepest levels, while each holds at most this many matches, run  */
-                             /* together in one workgroup (default 8192; 0 = one launch per level)   */
+                             /* together in one workgroup (default 2048; 0 = one launch per level)   */
     uint32_t long_copy;      /* matches longer than this are copied by a whole wave (16..2^21; 128)  */
     uint32_t xcd_parts;      /* contiguous parts of a level's matches, one per XCD (1..8; default 8) */
 } aceapex_tuning;

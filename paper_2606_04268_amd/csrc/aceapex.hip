@@ -66,7 +66,7 @@ constexpr uint32_t ROUND = 4;               // records per thread per round of k
 // Default schedule (each value can be changed per plan, see aceapex_tuning):
 constexpr uint32_t LONG_COPY = 128;         // matches longer than this are copied by a whole wave
 constexpr uint32_t LEVEL_WG_MAX = 512;      // workgroups of one level launch, at most
-constexpr uint32_t TAIL_LEVEL_MAX = 8192;   // levels with at most this many matches may join the tail
+constexpr uint32_t TAIL_LEVEL_MAX = 2048;   // levels with at most this many matches may join the tail
 constexpr uint32_t XCD_PARTS = 8;           // contiguous parts of a level's records, one per XCD
 constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
 constexpr uint64_t CHUNKS_MAX = 1ull << 24;  // chunks of one launch sequence (the k_parse grid), at most

@@ -109,7 +109,7 @@ def test_plan_argument_errors_need_no_gpu():
     info = _abi.probe(s)
     levels = _abi.level_table(s, info)
     t = _abi.tuning_defaults()
-    assert (t.level_wg_max, t.tail_level_max, t.long_copy, t.xcd_parts) == (512, 8192, 128, 8)
+    assert (t.level_wg_max, t.tail_level_max, t.long_copy, t.xcd_parts) == (512, 2048, 128, 8)
     lib = _abi.load()
     h = ctypes.c_void_p()
     with_table = _abi.Desc(_abi.Stream(16, info, levels), 4096, info.decoded_bytes, 0)
