@@ -37,8 +37,8 @@
 // once and replays the same launches, optionally as a captured HIP graph.
 //
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
-// their index; k_parse and k_level hand each XCD one contiguous range of
-// chunks / records so that neighbouring work shares an L2.
+// their index; k_level hands each XCD one contiguous range of a level's
+// records so that neighbouring work shares an L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -116,18 +116,6 @@ struct Batch {
     uint32_t long_copy;         // matches longer than this are copied by a whole wave
     uint32_t xcd_parts;         // k_level: contiguous parts of a level's records (1..8)
 };
-
-// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
-// their index.  xcd_slot maps the hardware index i of G workgroups to a
-// logical index such that every XCD receives one contiguous range, so that
-// neighbouring chunks and records -- and the cache lines they share -- stay
-// in one L2.
-__device__ __forceinline__ uint32_t xcd_slot(uint32_t i, uint32_t G)
-{
-    const uint32_t P = G < 8 ? G : 8;
-    const uint32_t x = i % P, k = i / P, q = G / P, r = G % P;
-    return x * q + min(x, r) + k;
-}
 
 __device__ __forceinline__ const Job &job_of(const Batch &B, uint32_t s) { return B.jobs ? B.jobs[s] : B.one; }
 
@@ -564,7 +552,11 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
 {
     __shared__ ParseLds<LH, STAGE> L;
     const uint32_t t = threadIdx.x, wave = t >> 6;
-    const uint32_t g = xcd_slot(blockIdx.x, gridDim.x);  // global chunk
+    // Chunks in dispatch order: workgroups finish roughly in that order, so
+    // each level's records are appended roughly in output order and every
+    // contiguous part of a level that k_level gives one XCD covers one
+    // stretch of the output.
+    const uint32_t g = blockIdx.x;  // global chunk
     const uint32_t sj = BATCH ? B.chunk_job[g] : 0u;     // its stream
     const Job &j = BATCH ? B.jobs[sj] : B.one;
     const uint32_t c = g - j.c0;
@@ -846,7 +838,8 @@ __global__ void __launch_bounds__(NT) k_seal(Batch B)
 
 // The level's slots are split into one contiguous part per XCD; the
 // workgroups of an XCD sweep its part together, tile after tile, so that the
-// destinations and sources they touch at one time share its L2.
+// destinations and sources they touch at one time share its L2.  Workgroup i
+// works on part i % P, which keeps each part on one XCD.
 template <bool BATCH>
 __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
 {
@@ -1659,7 +1652,7 @@ int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceap
     static const uint32_t wg[] = {512, 1024, 2048, 4096, 8192};
     static const uint32_t tail[] = {0, 2048, 8192, 32768};
     static const uint32_t longc[] = {32, 64, 128, 512};
-    static const uint32_t parts[] = {1, 8};
+    static const uint32_t parts[] = {1, 2, 4, 8};
     Tune cur = p->tune;
     float best_ms = 0.f;
     int rc = timed_run(cur, best_ms);

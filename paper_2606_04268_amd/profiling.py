@@ -62,7 +62,7 @@ def _rows(d: str):
 
 
 def _short(name: str) -> str:
-    m = re.search(r"::(k_\w+)\(", name)
+    m = re.search(r"::(k_\w+)[(<]", name)
     return m.group(1) if m else name.split("(")[0][:60]
 
 
