@@ -70,6 +70,7 @@ constexpr uint32_t TAIL_LEVEL_MAX = 2048;   // levels with at most this many mat
 constexpr uint32_t XCD_PARTS = 8;           // contiguous parts of a level's records, one per XCD
 constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
 constexpr uint64_t CHUNKS_MAX = 1ull << 24;  // chunks of one launch sequence (the k_parse grid), at most
+constexpr uint32_t COOP_RUNS = 8;          // k_parse: longer literal runs of a wave slot placed by the whole wave
 
 typedef uint16_t u16u __attribute__((aligned(1)));
 typedef uint32_t u32u __attribute__((aligned(1)));
@@ -283,17 +284,6 @@ __device__ __forceinline__ void load_records(const Batch &B, uint32_t r0, uint32
 
 // ------------------------------------------------------------------- scans
 
-__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t x)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
-
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x)
 {
     const int lane = threadIdx.x & 63;
@@ -324,61 +314,82 @@ __device__ uint64_t wg_excl_scan64(uint64_t v, uint64_t *tmp, uint64_t &total)
     return before + x - v;
 }
 
+// DPP control word of a whole-wave shift by one lane: lane i reads lane i-1,
+// and lane 0 keeps the old value.
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
 // One wave decodes exactly cnt LEB128 values (at most 4 bytes each) from the
-// global bytes p[0, nb) into vals[0, cnt).  Lane i reads bytes 4i..4i+3 of each
-// 256-byte window; a value ends at a byte below 0x80, and its earlier bytes
-// are found by walking back through the 8-byte window made of the lane's
-// dword and its left neighbour's.  Returns true (uniformly) iff the slice
-// holds exactly cnt well-formed values.
-__device__ bool wave_varints(const uint8_t *p, uint32_t nb, uint32_t cnt, uint32_t *vals)
+// global bytes p[0, nb) into vals[0, cnt); p[0, avail) may be read.  Lane i
+// holds bytes 4i..4i+3 of each 256-byte window, all loaded before any is
+// decoded.  A value ends at a byte below 0x80.  Values ending in lanes below
+// are counted with one ballot per byte position (no cross-lane scan), and
+// each value is assembled without branches from the 8 bytes made of the
+// lane's dword and its left neighbour's (one DPP move): it starts after the
+// last end byte among the three bytes before its own end byte.  Returns true
+// (uniformly) iff the slice holds exactly cnt well-formed values.
+__device__ __forceinline__ bool wave_varints(const uint8_t *p, uint32_t nb, uint32_t avail, uint32_t cnt,
+                                             uint32_t *vals)
 {
     constexpr uint32_t WINDOWS = (4 * (K_MAX + 1) + 255) / 256;  // the longest slice a chunk may hold
+    constexpr uint32_t WPRE = 8;  // windows loaded up front; later ones (slices over 2 KiB) when decoded
     const uint32_t lane = threadIdx.x & 63;
-    // every window's dword is loaded before any is decoded
-    uint32_t v[WINDOWS];
-#pragma unroll
-    for (uint32_t i = 0; i < WINDOWS; i++) {
+    auto load = [&](uint32_t i) {
         const uint32_t o = 256 * i + 4 * lane;
-        if (o + 4 <= nb) {
-            v[i] = ld32(p + o);
-        } else {
-            v[i] = 0x80808080u;  // bytes past the slice: continuation, never a value end
-            for (uint32_t k = 0; k < 4; k++)
-                if (o + k < nb) v[i] = (v[i] & ~(0xffu << (8 * k))) | ((uint32_t)p[o + k] << (8 * k));
+        uint32_t x = 0x80808080u;  // bytes past the slice: continuation, never a value end
+        if (o < nb) {
+            if (o + 4 <= avail) {
+                x = ld32(p + o);
+            } else {  // the last bytes of the stream
+                x = 0;
+                for (uint32_t k = 0; k < 4; k++)
+                    if (o + k < avail) x |= (uint32_t)p[o + k] << (8 * k);
+            }
+            if (o + 4 > nb) {
+                const uint32_t keep = (1u << (8 * (nb - o))) - 1;
+                x = (x & keep) | (0x80808080u & ~keep);
+            }
         }
-    }
-    uint32_t prev_last = 0;  // dword left of the window; zero bytes end any backward walk
+        return x;
+    };
+    uint32_t v[WPRE];
+#pragma unroll
+    for (uint32_t i = 0; i < WPRE; i++) v[i] = load(i);
+    uint32_t prev_last = 0;  // dword left of the window; zero bytes end any value before the slice
     uint32_t base = 0;
     bool ok = nb <= 256 * WINDOWS;
+    const uint32_t last = nb - 1;  // the slice's last byte must end a value
 #pragma unroll
     for (uint32_t i = 0; i < WINDOWS; i++) {
-        if (256 * i >= nb) continue;  // (uniform) past the slice
-        const uint32_t term = ~v[i] & 0x80808080u;
-        const uint32_t c = __popc(term);
-        const uint32_t incl = wave_incl_scan32(c);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        uint32_t pv = __shfl_up(v[i], 1, 64);
-        if (lane == 0) pv = prev_last;
-        const uint64_t win = ((uint64_t)v[i] << 32) | pv;
-        uint32_t idx = base + incl - c;
+        if (256 * i >= nb) break;  // (uniform) past the slice
+        const uint32_t x = i < WPRE ? v[i] : load(i);
+        const uint32_t o = 256 * i + 4 * lane;
+        const uint32_t pv = (uint32_t)__builtin_amdgcn_update_dpp((int)prev_last, (int)x, DPP_WAVE_SHR1, 0xf, 0xf, false);
+        const uint32_t term = ~x & 0x80808080u;
+        uint32_t idx = base, tot = 0;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            if (!(term & (0x80u << (8 * k)))) continue;
-            uint32_t val = (v[i] >> (8 * k)) & 0x7f;
-            int q = 3 + k, n = 0;
-            for (; n < 4; n++, q--) {
-                const uint32_t byte = (uint32_t)(win >> (8 * q)) & 0xff;
-                if (byte < 0x80) break;
-                val = (val << 7) | (byte & 0x7f);
+        for (uint32_t k = 0; k < 4; k++) {
+            const uint64_t m = __ballot(term & (0x80u << (8 * k)));
+            idx += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            tot += (uint32_t)__popcll(m);
+        }
+        if (o <= last && last < o + 4 && ((x >> (8 * (last - o) + 7)) & 1)) ok = false;
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++) {
+            // bytes k+1 .. k+4 of the window pv:x; the top one (byte k of x) ends the value
+            const uint32_t y4 = k == 3 ? x : __builtin_amdgcn_alignbyte(x, pv, k + 1);
+            const uint32_t ends = ~y4 & 0x00808080u;  // end bytes among the three before it
+            const uint32_t y = y4 >> (32 - __clz(ends));  // the value's bytes, first one lowest
+            const uint32_t val = (y & 0x7fu) | ((y >> 1) & 0x3f80u) | ((y >> 2) & 0x1fc000u) | ((y >> 3) & 0xfe00000u);
+            if (term & (0x80u << (8 * k))) {
+                if (ends == 0 && ((pv >> (8 * k + 7)) & 1)) ok = false;  // a fifth byte
+                if (idx < cnt) vals[idx] = val;
+                idx++;
             }
-            if (n > 3) ok = false;
-            if (idx < cnt) vals[idx] = val;
-            idx++;
         }
         base += tot;
-        prev_last = __shfl(v[i], 63, 64);
+        prev_last = __builtin_amdgcn_readlane(x, 63);
     }
-    ok = ok && base == cnt && (nb == 0 || p[nb - 1] < 0x80);
+    ok = ok && base == cnt;
     return __ballot(!ok) == 0;
 }
 
@@ -540,7 +551,7 @@ struct ParseLds {
         } v;
         uint8_t tile[TILE_BYTES];      // after the scan: the chunk's output span, literals in place
     } u;
-    uint32_t stage[STAGE / 4 + 4];  // the chunk's literal bytes from a 16-byte boundary
+    uint32_t stage[STAGE / 4 + 8];  // the chunk's literal bytes from a 16-byte boundary (+ read slack)
     uint32_t lcount[LH];         // matches of the chunk per level (levels < LH)
     uint32_t lbase[LH];          // record slot reserved for them
     uint64_t tmp[NT / 64];
@@ -548,7 +559,7 @@ struct ParseLds {
 } __attribute__((aligned(16)));
 
 template <bool BATCH, uint32_t LH, uint32_t STAGE>
-__global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
+__global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
 {
     __shared__ ParseLds<LH, STAGE> L;
     const uint32_t t = threadIdx.x, wave = t >> 6;
@@ -615,15 +626,9 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
     const bool tail_cmd = ncmd > NT * PER;
 
     // this thread's sequences e0 .. e0+3: run, match length and level
-    uint32_t r[PER], m[PER], l[PER], src[PER];
+    uint32_t r[PER], m[PER], l[PER];
     uint32_t rt = 0;  // the trailing run when tail_cmd (uniform)
     bool bad = false;
-    {
-        const u128u o4 = e0 + PER <= ns ? *(const u128u *)(j.comp + d.off_at + 4 * e0) : u128u{0, 0, 0, 0};
-        src[0] = o4.a; src[1] = o4.b; src[2] = o4.c; src[3] = o4.d;
-        if (e0 + PER > ns)
-            for (uint32_t u = 0; u < PER; u++) src[u] = e0 + u < ns ? ld32(j.comp + d.off_at + 4 * (e0 + u)) : 0;
-    }
     if (one_byte) {
         const uint32_t cw = bytes4(j.comp + d.cmd_at, e0, ncmd);
         const uint32_t lw = bytes4(j.comp + d.len_at, e0, ns);
@@ -641,13 +646,18 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
         }
     } else {
         bool ok = true;
-        if (wave == 0) ok = wave_varints(j.comp + d.cmd_at, d.cmd_n, ncmd, L.u.v.run);
-        else if (wave == 1) ok = wave_varints(j.comp + d.len_at, d.len_n, ns, L.u.v.mlen);
-        else if (wave == 2) ok = wave_varints(j.comp + d.lvl_at, d.lvl_n, ns, L.u.v.lvl);
+        const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
+        if (wv < 3) {  // waves 0, 1, 2: the cmd, len and lvl slices
+            const uint32_t at = wv == 0 ? d.cmd_at : wv == 1 ? d.len_at : d.lvl_at;
+            const uint32_t nb = wv == 0 ? d.cmd_n : wv == 1 ? d.len_n : d.lvl_n;
+            uint32_t *vals = wv == 0 ? L.u.v.run : wv == 1 ? L.u.v.mlen : L.u.v.lvl;
+            ok = wave_varints(j.comp + at, nb, j.comp_bytes - at, wv == 0 ? ncmd : ns, vals);
+        }
         if (!ok && (t & 63) == 0) L.bad = 1;
         __syncthreads();
         if (L.bad) {
             if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
+            if (staged) __builtin_amdgcn_s_waitcnt(0);  // no direct-to-LDS load left in flight at exit
             return;
         }
 #pragma unroll
@@ -680,17 +690,28 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
         return;
     }
 
+    // the match sources, needed only by the records: loaded here, so that
+    // they are not held through the varint decode and arrive while the
+    // literals are placed
+    uint32_t src[PER];
+    {
+        const u128u o4 = e0 + PER <= ns ? *(const u128u *)(j.comp + d.off_at + 4 * e0) : u128u{0, 0, 0, 0};
+        src[0] = o4.a; src[1] = o4.b; src[2] = o4.c; src[3] = o4.d;
+        if (e0 + PER > ns)
+            for (uint32_t u = 0; u < PER; u++) src[u] = e0 + u < ns ? ld32(j.comp + d.off_at + 4 * (e0 + u)) : 0;
+    }
+
     uint32_t pos = d.out_base + (uint32_t)(ex >> 32), lq = (uint32_t)ex;
     uint32_t dst[PER], rank[PER];
+    uint32_t cw[PER], ce[PER], cq[PER];  // staged runs: tile words [cw, ce) still to place, staged byte of cw
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
+        cw[u] = ce[u] = cq[u] = 0;
         if (r[u] && staged) {
-            const uint32_t a0 = pos - base16, w0 = a0 & ~3u, w1 = (a0 + r[u] + 3) & ~3u;
-            const uint32_t q0 = (uint32_t)((uint64_t)d.lit_at + lq - (a0 - w0) - la);  // staged byte for tile byte w0
-            for (uint32_t o = w0; o < w1; o += 4) {
-                const uint32_t q = q0 + (o - w0);
-                *(uint32_t *)(L.u.tile + o) = __builtin_amdgcn_alignbyte(L.stage[(q >> 2) + 1], L.stage[q >> 2], q & 3);
-            }
+            const uint32_t a0 = pos - base16;
+            cw[u] = a0 & ~3u;
+            ce[u] = (a0 + r[u] + 3) & ~3u;
+            cq[u] = (uint32_t)((uint64_t)d.lit_at + lq - (a0 - cw[u]) - la);
         } else if (r[u] && words) {
             const uint32_t a0 = pos - base16, w0 = a0 & ~3u, w1 = (a0 + r[u] + 3) & ~3u;
             const uint64_t s0 = (uint64_t)d.lit_at + lq - (a0 - w0);  // stream byte that lands on tile byte w0
@@ -732,6 +753,63 @@ __global__ void __launch_bounds__(NT, 6) k_parse(Batch B)
         lq += r[u];
         dst[u] = pos;
         pos += m[u];
+    }
+    if (staged) {
+        // The staged runs.  Each lane places the first four words of each of
+        // its runs.  The words past those of the longer runs are then placed
+        // per run slot u: when only a few lanes have a longer run in slot u,
+        // the whole wave places those runs one at a time, a word per lane, so
+        // that a long run costs one step instead of holding its lane for many;
+        // otherwise every lane places the rest of its own run, four words per
+        // pass.
+        uint32_t sw[PER][5];  // every run's first staged words, read at once
+#pragma unroll
+        for (uint32_t u = 0; u < PER; u++)
+#pragma unroll
+            for (uint32_t k = 0; k < 5; k++) sw[u][k] = L.stage[(cq[u] >> 2) + k];
+#pragma unroll
+        for (uint32_t u = 0; u < PER; u++) {
+            const uint32_t w = cw[u], e = ce[u], sh = cq[u] & 3;
+            uint32_t *tw = (uint32_t *)(L.u.tile + w);
+            if (w < e) tw[0] = __builtin_amdgcn_alignbyte(sw[u][1], sw[u][0], sh);
+            if (w + 4 < e) tw[1] = __builtin_amdgcn_alignbyte(sw[u][2], sw[u][1], sh);
+            if (w + 8 < e) tw[2] = __builtin_amdgcn_alignbyte(sw[u][3], sw[u][2], sh);
+            if (w + 12 < e) tw[3] = __builtin_amdgcn_alignbyte(sw[u][4], sw[u][3], sh);
+        }
+        const uint32_t lane = t & 63;
+#pragma unroll
+        for (uint32_t u = 0; u < PER; u++) {
+            uint64_t m = __ballot(cw[u] + 16 < ce[u]);
+            if (__popcll(m) <= COOP_RUNS) {
+                for (; m; m &= m - 1) {
+                    const uint32_t src_lane = (uint32_t)__builtin_ctzll(m);
+                    const uint32_t w = __builtin_amdgcn_readlane(cw[u], src_lane) + 16;
+                    const uint32_t e = __builtin_amdgcn_readlane(ce[u], src_lane);
+                    const uint32_t q = __builtin_amdgcn_readlane(cq[u], src_lane) + 16;
+                    for (uint32_t o = 4 * lane; w + o < e; o += 256) {
+                        const uint32_t qq = q + o;
+                        *(uint32_t *)(L.u.tile + w + o) =
+                            __builtin_amdgcn_alignbyte(L.stage[(qq >> 2) + 1], L.stage[qq >> 2], qq & 3);
+                    }
+                }
+            } else {
+                const uint32_t e = ce[u];
+                for (uint32_t w = cw[u] + 16, q = cq[u] + 16;; w += 16, q += 16) {
+                    const bool act = w < e;
+                    if (__ballot(act) == 0) break;
+                    if (act) {
+                        const uint32_t qi = q >> 2, sh = q & 3;
+                        const uint32_t s0 = L.stage[qi], s1 = L.stage[qi + 1], s2 = L.stage[qi + 2],
+                                       s3 = L.stage[qi + 3], s4 = L.stage[qi + 4];
+                        uint32_t *tw = (uint32_t *)(L.u.tile + w);
+                        tw[0] = __builtin_amdgcn_alignbyte(s1, s0, sh);
+                        if (w + 4 < e) tw[1] = __builtin_amdgcn_alignbyte(s2, s1, sh);
+                        if (w + 8 < e) tw[2] = __builtin_amdgcn_alignbyte(s3, s2, sh);
+                        if (w + 12 < e) tw[3] = __builtin_amdgcn_alignbyte(s4, s3, sh);
+                    }
+                }
+            }
+        }
     }
     if (rt) {  // the trailing run of a full chunk, copied by the whole workgroup
         const uint32_t at = d.out_base + d.out_len - rt;
