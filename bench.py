@@ -24,6 +24,10 @@ Other modes (one JSON line each):
                   64 KiB..256 MiB, same mix) under a 200 GB device-memory
                   budget, continuous batching against one-request-at-a-time,
                   swept over offered loads; p50 / p99 latency and decoded GB/s.
+  --mode sweep    The encoder's depth limit D (1, 2, 10, unlimited) against
+                  chain flattening (off, R1, R2) on wiki-like text and
+                  FASTQ-like data (32 MiB each): stream ratio, deepest level
+                  and decoded GB/s of each stream (Sec. 7.4, Table 5).
 """
 from __future__ import annotations
 
@@ -398,6 +402,70 @@ def print_algorithmic(args):
     print(json.dumps(algorithmic_bytes_per_group(stream_stats(s))))
 
 
+def run_sweep(args):
+    """Depth limit D x chain flattening on two content kinds: for each stream,
+    the ratio (original / stream bytes), the deepest level and the decoded
+    GB/s of a plan replayed as a HIP graph, each decode checked byte for byte."""
+    import torch
+
+    import synth
+    import paper_2606_04268_amd as ax
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for kind, seed in (("wiki", 0xACE2), ("fastq", 0xACE1)):
+        x = synth.make(kind, args.sweep_mib << 20, seed)
+        x_dev = torch.from_numpy(x).to(dev)
+        for depth in (1, 2, 10, 0):
+            for flatten in (0, 1, 2):
+                t0 = time.perf_counter()
+                s = ax.encode(x, max_depth=depth, flatten=flatten, threads=8)
+                enc_s = time.perf_counter() - t0
+                ds = ax.to_device(s, dev)
+                out = torch.empty(ds.n, dtype=torch.uint8, device=dev)
+                status = torch.zeros(1, dtype=torch.int32, device=dev)
+                plan = ax.Plan([ds], [out], status, stream=stream)
+                try:
+                    plan.launch(stream=stream, graph=True)
+                    torch.cuda.synchronize()
+                    ax.check_status(status)
+                    if not torch.equal(out, x_dev):
+                        raise AssertionError(f"sweep {kind} D={depth} flatten={flatten}: decode differs")
+                    for _ in range(max(1, args.warmup)):
+                        plan.launch(stream=stream, graph=True)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(args.steps):
+                        plan.launch(stream=stream, graph=True)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / args.steps
+                    ax.check_status(status)
+                    if not torch.equal(out, x_dev):
+                        raise AssertionError(f"sweep {kind} D={depth} flatten={flatten}: timed decode differs")
+                finally:
+                    plan.close()
+                row = {"kind": kind, "depth_limit": depth or None, "flatten": ["off", "R1", "R2"][flatten],
+                       "ratio": round(x.size / s.size, 4), "max_level": int(ds.info.max_level),
+                       "ms": round(ms, 4), "gbps": round(x.size / (ms * 1e-3) / 1e9, 2), "encode_s": round(enc_s, 1)}
+                rows.append(row)
+                log(f"sweep: {row}")
+                del out, ds
+    best = max(rows, key=lambda r: r["gbps"])
+    line = {
+        "metric": METRIC, "value": best["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"sweep: wiki-like text and FASTQ-like data, {args.sweep_mib} MiB each; depth limit "
+                               "1/2/10/unlimited x flattening off/R1/R2; value = the fastest stream"},
+        "bit_exact": {"device_compare": True},
+        "sweep": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,7 +474,8 @@ def main():
     ap.add_argument("--workload", default="fastq256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plan", action="store_true", help="plain mode: skip the plan + graph leg")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "served", "algorithmic"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "served", "sweep", "algorithmic"])
+    ap.add_argument("--sweep-mib", type=int, default=32, help="sweep: MiB per workload")
     ap.add_argument("--streams", type=int, default=4096, help="batched: descriptors per call")
     ap.add_argument("--distinct", type=int, default=256, help="batched: distinct encoded streams")
     ap.add_argument("--loads", default="10,25,50,100,150,200", help="served: offered GB/s sweep")
@@ -424,6 +493,8 @@ def main():
         return run_batched(args)
     if args.mode == "served":
         return run_served(args)
+    if args.mode == "sweep":
+        return run_sweep(args)
 
     import numpy as np
     import torch

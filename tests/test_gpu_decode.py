@@ -108,6 +108,36 @@ def test_padded_varints(width):
     parity(np.frombuffer(want, np.uint8), s, f"padded varints random tokens width={width}")
 
 
+def test_long_literal_runs_in_staged_chunks():
+    """Chunks whose literals are staged in LDS, with the run-length patterns
+    that select each way of placing the words past a run's first four: a few
+    very long runs in a wave (placed by the whole wave, several 256-byte steps
+    for the 2000-byte run), twelve lanes per wave with a 40-byte run in one
+    slot and every lane with a 20-byte run in another (placed by each lane,
+    four words per pass), and exactly eight lanes with a 100-byte run."""
+    rng = np.random.default_rng(41)
+    runs = []
+    for i in range(1024):  # chunk 0: three very long runs among one-byte runs
+        runs.append({5: 700, 300: 2000, 777: 300}.get(i, 1))
+    for i in range(1024):  # chunk 1: twelve lanes per wave with a 40-byte run in slot 0
+        runs.append(40 if i % 4 == 0 and (i // 4) % 64 < 12 else int(rng.integers(0, 3)))
+    for i in range(1024):  # chunk 2: exactly eight lanes per wave with a 100-byte run in slot 1
+        runs.append(100 if i % 4 == 1 and (i // 4) % 64 < 8 else int(rng.integers(0, 4)))
+    for i in range(1024):  # chunk 3: every lane has a 20-byte run in slot 2
+        runs.append(20 if i % 4 == 2 else int(rng.integers(0, 2)))
+    runs[0] = max(runs[0], 8)
+    seqs, pos = [], 0
+    for r in runs:
+        pos += r
+        seqs.append((r, 4, int(rng.integers(0, pos - 3))))
+        pos += 4
+    trail = 5
+    n = pos + trail
+    lits = bytes(rng.integers(0, 256, size=n, dtype=np.uint8))
+    s, want = streamgen.build([(seqs, trail)], lits, n, block_log2=20, chunk_log2=10)
+    parity(np.frombuffer(want, np.uint8), s, "long literal runs")
+
+
 def test_doubling_string_long_matches():
     u = np.random.default_rng(7).permutation(256)[:16].astype(np.uint8).tobytes()
     x = u * (1 << 16)  # 1 MiB of one repeated 16-byte unit: long matches, deep levels
