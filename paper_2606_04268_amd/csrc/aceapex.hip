@@ -53,7 +53,8 @@
 namespace {
 
 constexpr int NT = 256;                     // threads per workgroup
-constexpr int NT_TAIL = 1024;               // threads of the tail workgroup
+constexpr int NT_TAIL = 512;                // threads of the tail workgroup
+constexpr uint32_t TAIL_RANGES = 8192;      // tail levels whose slot ranges k_tail keeps in LDS
 constexpr uint32_t K_LOG2_MAX = 10;         // sequences per chunk, at most
 constexpr uint32_t K_MAX = 1u << K_LOG2_MAX;
 constexpr uint32_t PER = K_MAX / NT;        // sequences per thread in k_parse
@@ -169,11 +170,12 @@ __device__ __forceinline__ void wave_copy(uint8_t *d, const uint8_t *s, uint32_t
 // the match are read and discarded) and exact stores; all loads of the round
 // are issued before the stores.  Matches up to long_copy bytes are copied by
 // their own lane; longer ones are then copied by the whole wave, one at a time.
-__device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *on, int32_t *const *sp,
-                                            const uint32_t *dst, const uint32_t *src, uint32_t *len,
-                                            uint32_t long_copy)
+// run_loads issues the source loads (and rejects records that do not fit);
+// run_stores does the rest, so that other loads may be issued in between.
+__device__ __forceinline__ void run_loads(const uint32_t *on, int32_t *const *sp, uint8_t *const *ob,
+                                          const uint32_t *dst, const uint32_t *src, uint32_t *len,
+                                          uint64_t *lo, uint64_t *hi)
 {
-    uint64_t lo[ROUND], hi[ROUND];
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
         if (len[u] && ((uint64_t)dst[u] + len[u] > on[u] || (uint64_t)src[u] + len[u] > dst[u])) {
@@ -188,6 +190,12 @@ __device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *
             hi[u] = ((uint64_t)v.d << 32) | v.c;
         }
     }
+}
+
+__device__ __forceinline__ void run_stores(uint8_t *const *ob, const uint32_t *on, const uint32_t *dst,
+                                           const uint32_t *src, const uint32_t *len, const uint64_t *lo,
+                                           const uint64_t *hi, uint32_t long_copy)
+{
 #pragma unroll
     for (uint32_t u = 0; u < ROUND; u++) {
         if (!len[u]) continue;
@@ -209,6 +217,15 @@ __device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *
             wave_copy(o + d0, o + s0, n0);
         }
     }
+}
+
+__device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *on, int32_t *const *sp,
+                                            const uint32_t *dst, const uint32_t *src, uint32_t *len,
+                                            uint32_t long_copy)
+{
+    uint64_t lo[ROUND], hi[ROUND];
+    run_loads(on, sp, ob, dst, src, len, lo, hi);
+    run_stores(ob, on, dst, src, len, lo, hi, long_copy);
 }
 
 // Slots [lo, hi) of level k: in a single-stream decode the filled part of the
@@ -938,15 +955,28 @@ __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
 }
 
 // The tail of deep levels [k0, max_level] in one workgroup of NT_TAIL
-// threads.  The first round of the next level's records is fetched before the
-// current level's copies, so that after each barrier only the source reads
-// remain.
+// threads.  The slot ranges of the first TAIL_RANGES tail levels are read into
+// LDS once, so that each level's first round of records is fetched at the
+// start of the level before it, with no dependent load in front; after each
+// barrier only the source reads remain.
 template <bool BATCH>
 __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
 {
+    __shared__ uint32_t rlo[TAIL_RANGES], rhi[TAIL_RANGES];
+    const uint32_t nt = B.max_level + 1 - k0;  // tail levels
+    for (uint32_t i = threadIdx.x; i < min(nt, TAIL_RANGES); i += NT_TAIL) level_range(B, k0 + i, rlo[i], rhi[i]);
+    __syncthreads();
+    auto range = [&](uint32_t k, uint32_t &lo, uint32_t &hi) {
+        if (k - k0 < TAIL_RANGES) {
+            lo = rlo[k - k0];
+            hi = rhi[k - k0];
+        } else {
+            level_range(B, k, lo, hi);
+        }
+    };
     uint32_t nd[ROUND], nsr[ROUND], nlj[ROUND];
     uint32_t lo, hi;
-    level_range(B, k0, lo, hi);
+    range(k0, lo, hi);
     fetch_records(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd, nsr, nlj);
     for (uint32_t k = k0; k <= B.max_level; k++) {
         const uint32_t lo_k = lo, hi_k = hi;
@@ -954,7 +984,7 @@ __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
 #pragma unroll
         for (uint32_t u = 0; u < ROUND; u++) { dst[u] = nd[u]; src[u] = nsr[u]; lj[u] = nlj[u]; }
         if (k < B.max_level) {
-            level_range(B, k + 1, lo, hi);
+            range(k + 1, lo, hi);
             fetch_records(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd,
                           nsr, nlj);
         }
