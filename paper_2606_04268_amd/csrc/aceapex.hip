@@ -301,14 +301,27 @@ __device__ __forceinline__ void load_records(const Batch &B, uint32_t r0, uint32
 
 // ------------------------------------------------------------------- scans
 
+// DPP moves of one 64-bit value (two 32-bit halves); lanes the control word
+// leaves without a source, or disables by row_mask, read 0.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scan over the 64 lanes of a wave with DPP moves only (no LDS):
+// row_shr 1, 2, 4, 8 scan each row of 16 lanes, then row_bcast 15 and 31 add
+// the totals of the rows below.
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint64_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    x += dpp64<0x111, 0xf, true>(x);  // row_shr:1
+    x += dpp64<0x112, 0xf, true>(x);  // row_shr:2
+    x += dpp64<0x114, 0xf, true>(x);  // row_shr:4
+    x += dpp64<0x118, 0xf, true>(x);  // row_shr:8
+    x += dpp64<0x142, 0xa, false>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp64<0x143, 0xc, false>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
 
