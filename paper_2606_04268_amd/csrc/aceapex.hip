@@ -63,7 +63,8 @@ constexpr uint32_t BLOCK_LOG2_MAX = 20;
 constexpr uint32_t LEN_BITS = 21;           // a match length needs 21 bits (blocks of at most 2^20 bytes)
 constexpr uint32_t LEN_MASK = (1u << LEN_BITS) - 1;
 constexpr uint32_t JOBS_MAX = 1u << (32 - LEN_BITS);  // streams per launch sequence
-constexpr uint32_t ROUND = 4;               // records per thread per round of k_level / k_tail
+constexpr uint32_t ROUND_LEVEL = 2;         // records per thread per round of k_level on levels beyond one per thread
+constexpr uint32_t ROUND_TAIL = 4;          // records per thread per round of k_tail
 // Default schedule (each value can be changed per plan, see aceapex_tuning):
 constexpr uint32_t LONG_COPY = 128;         // matches longer than this are copied by a whole wave
 constexpr uint32_t LEVEL_WG_MAX = 512;      // workgroups of one level launch, at most
@@ -164,7 +165,7 @@ __device__ __forceinline__ void wave_copy(uint8_t *d, const uint8_t *s, uint32_t
     for (uint32_t o = lane * 16; o < n; o += 64 * 16) copy_bytes(d + o, s + o, min(16u, n - o));
 }
 
-// Run up to ROUND match records held by this thread, each into its own
+// Run up to R match records held by this thread, each into its own
 // stream's output ob[u] of on[u] bytes.  Matches of at most 16 bytes take one
 // 16-byte load of their source (when 16 bytes are there to read: bytes past
 // the match are read and discarded) and exact stores; all loads of the round
@@ -172,12 +173,13 @@ __device__ __forceinline__ void wave_copy(uint8_t *d, const uint8_t *s, uint32_t
 // their own lane; longer ones are then copied by the whole wave, one at a time.
 // run_loads issues the source loads (and rejects records that do not fit);
 // run_stores does the rest, so that other loads may be issued in between.
+template <uint32_t R>
 __device__ __forceinline__ void run_loads(const uint32_t *on, int32_t *const *sp, uint8_t *const *ob,
                                           const uint32_t *dst, const uint32_t *src, uint32_t *len,
                                           uint64_t *lo, uint64_t *hi)
 {
 #pragma unroll
-    for (uint32_t u = 0; u < ROUND; u++) {
+    for (uint32_t u = 0; u < R; u++) {
         if (len[u] && ((uint64_t)dst[u] + len[u] > on[u] || (uint64_t)src[u] + len[u] > dst[u])) {
             atomicCAS(sp[u], 0, ACEAPEX_E_CORRUPT);
             len[u] = 0;
@@ -192,12 +194,13 @@ __device__ __forceinline__ void run_loads(const uint32_t *on, int32_t *const *sp
     }
 }
 
+template <uint32_t R>
 __device__ __forceinline__ void run_stores(uint8_t *const *ob, const uint32_t *on, const uint32_t *dst,
                                            const uint32_t *src, const uint32_t *len, const uint64_t *lo,
                                            const uint64_t *hi, uint32_t long_copy)
 {
 #pragma unroll
-    for (uint32_t u = 0; u < ROUND; u++) {
+    for (uint32_t u = 0; u < R; u++) {
         if (!len[u]) continue;
         if (len[u] <= 16 && (uint64_t)src[u] + 16 <= on[u]) {
             store_upto16(ob[u] + dst[u], lo[u], hi[u], len[u]);
@@ -206,7 +209,7 @@ __device__ __forceinline__ void run_stores(uint8_t *const *ob, const uint32_t *o
         }
     }
 #pragma unroll
-    for (uint32_t u = 0; u < ROUND; u++) {
+    for (uint32_t u = 0; u < R; u++) {
         uint64_t m = __ballot(len[u] > long_copy);
         while (m) {
             const int lane = __ffsll((unsigned long long)m) - 1;
@@ -219,13 +222,14 @@ __device__ __forceinline__ void run_stores(uint8_t *const *ob, const uint32_t *o
     }
 }
 
+template <uint32_t R>
 __device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *on, int32_t *const *sp,
                                             const uint32_t *dst, const uint32_t *src, uint32_t *len,
                                             uint32_t long_copy)
 {
-    uint64_t lo[ROUND], hi[ROUND];
-    run_loads(on, sp, ob, dst, src, len, lo, hi);
-    run_stores(ob, on, dst, src, len, lo, hi, long_copy);
+    uint64_t lo[R], hi[R];
+    run_loads<R>(on, sp, ob, dst, src, len, lo, hi);
+    run_stores<R>(ob, on, dst, src, len, lo, hi, long_copy);
 }
 
 // Slots [lo, hi) of level k: in a single-stream decode the filled part of the
@@ -242,13 +246,14 @@ __device__ __forceinline__ void level_range(const Batch &B, uint32_t k, uint32_t
     }
 }
 
-// Raw words of the records r0 + u*stride (u < ROUND), without waiting
+// Raw words of the records r0 + u*stride (u < R), without waiting
 // between them; a slot at or past r_end gets lj = 0 (no match).
+template <uint32_t R>
 __device__ __forceinline__ void fetch_records(const Batch &B, uint32_t r0, uint32_t stride, uint32_t r_end,
                                               uint32_t *dst, uint32_t *src, uint32_t *lj)
 {
 #pragma unroll
-    for (uint32_t u = 0; u < ROUND; u++) {
+    for (uint32_t u = 0; u < R; u++) {
         const uint32_t i = r0 + u * stride;
         const bool ok = i < r_end;
         const uint32_t *r = B.recs + 3ull * (ok ? i : r0);
@@ -261,12 +266,12 @@ __device__ __forceinline__ void fetch_records(const Batch &B, uint32_t r0, uint3
 // The stream of each fetched record: its output, size and status.  In a
 // batch every slot of a level was filled in this decode or given length 0 by
 // k_seal, so the stream index carried by the record is all that is needed.
-template <bool BATCH>
+template <bool BATCH, uint32_t R>
 __device__ __forceinline__ void resolve_records(const Batch &B, const uint32_t *lj, uint8_t **ob, uint32_t *on,
                                                 int32_t **sp, uint32_t *len)
 {
 #pragma unroll
-    for (uint32_t u = 0; u < ROUND; u++) {
+    for (uint32_t u = 0; u < R; u++) {
         len[u] = lj[u] & LEN_MASK;
         if (!BATCH) {
             ob[u] = B.one.out;
@@ -288,15 +293,15 @@ __device__ __forceinline__ void resolve_records(const Batch &B, const uint32_t *
     }
 }
 
-// Fetch and resolve ROUND records (see fetch_records, resolve_records).
-template <bool BATCH>
+// Fetch and resolve R records (see fetch_records, resolve_records).
+template <bool BATCH, uint32_t R>
 __device__ __forceinline__ void load_records(const Batch &B, uint32_t r0, uint32_t stride,
                                              uint32_t r_end, uint8_t **ob, uint32_t *on, int32_t **sp,
                                              uint32_t *dst, uint32_t *src, uint32_t *len)
 {
-    uint32_t lj[ROUND];
-    fetch_records(B, r0, stride, r_end, dst, src, lj);
-    resolve_records<BATCH>(B, lj, ob, on, sp, len);
+    uint32_t lj[R];
+    fetch_records<R>(B, r0, stride, r_end, dst, src, lj);
+    resolve_records<BATCH, R>(B, lj, ob, on, sp, len);
 }
 
 // ------------------------------------------------------------------- scans
@@ -944,11 +949,14 @@ __global__ void __launch_bounds__(NT) k_seal(Batch B)
 
 // --------------------------------------------------------------- k_level
 
+// One level: each thread takes R records per round (R = 1 while the level
+// fits the launch at one record per thread, so that a mid-size level is
+// spread over as many workgroups as it can use; R = 2 for larger levels).
 // The level's slots are split into one contiguous part per XCD; the
 // workgroups of an XCD sweep its part together, tile after tile, so that the
 // destinations and sources they touch at one time share its L2.  Workgroup i
 // works on part i % P, which keeps each part on one XCD.
-template <bool BATCH>
+template <bool BATCH, uint32_t R>
 __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
 {
     uint32_t R0, R1;
@@ -957,13 +965,13 @@ __global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
     const uint32_t x = blockIdx.x % P, w = blockIdx.x / P, W = (G - x + P - 1) / P;
     const uint64_t S = R1 > R0 ? R1 - R0 : 0;
     const uint32_t p0 = R0 + (uint32_t)(S * x / P), p1 = R0 + (uint32_t)(S * (x + 1) / P);
-    for (uint32_t r0 = p0 + w * (NT * ROUND) + threadIdx.x;; r0 += W * (NT * ROUND)) {
+    for (uint32_t r0 = p0 + w * (NT * R) + threadIdx.x;; r0 += W * (NT * R)) {
         if (__ballot(r0 < p1) == 0) break;
-        uint8_t *ob[ROUND];
-        int32_t *sp[ROUND];
-        uint32_t on[ROUND], dst[ROUND], src[ROUND], len[ROUND];
-        load_records<BATCH>(B, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
-        run_records(ob, on, sp, dst, src, len, B.long_copy);
+        uint8_t *ob[R];
+        int32_t *sp[R];
+        uint32_t on[R], dst[R], src[R], len[R];
+        load_records<BATCH, R>(B, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
+        run_records<R>(ob, on, sp, dst, src, len, B.long_copy);
     }
 }
 
@@ -987,29 +995,29 @@ __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
             level_range(B, k, lo, hi);
         }
     };
-    uint32_t nd[ROUND], nsr[ROUND], nlj[ROUND];
+    uint32_t nd[ROUND_TAIL], nsr[ROUND_TAIL], nlj[ROUND_TAIL];
     uint32_t lo, hi;
     range(k0, lo, hi);
-    fetch_records(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd, nsr, nlj);
+    fetch_records<ROUND_TAIL>(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd, nsr, nlj);
     for (uint32_t k = k0; k <= B.max_level; k++) {
         const uint32_t lo_k = lo, hi_k = hi;
-        uint32_t dst[ROUND], src[ROUND], lj[ROUND];
+        uint32_t dst[ROUND_TAIL], src[ROUND_TAIL], lj[ROUND_TAIL];
 #pragma unroll
-        for (uint32_t u = 0; u < ROUND; u++) { dst[u] = nd[u]; src[u] = nsr[u]; lj[u] = nlj[u]; }
+        for (uint32_t u = 0; u < ROUND_TAIL; u++) { dst[u] = nd[u]; src[u] = nsr[u]; lj[u] = nlj[u]; }
         if (k < B.max_level) {
             range(k + 1, lo, hi);
-            fetch_records(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd,
+            fetch_records<ROUND_TAIL>(B, hi ? min(lo + threadIdx.x, hi - 1) : 0, NT_TAIL, lo + threadIdx.x < hi ? hi : 0, nd,
                           nsr, nlj);
         }
-        uint8_t *ob[ROUND];
-        int32_t *sp[ROUND];
-        uint32_t on[ROUND], len[ROUND];
-        resolve_records<BATCH>(B, lj, ob, on, sp, len);
-        run_records(ob, on, sp, dst, src, len, B.long_copy);
-        for (uint32_t r = lo_k + ROUND * NT_TAIL + threadIdx.x;; r += ROUND * NT_TAIL) {
+        uint8_t *ob[ROUND_TAIL];
+        int32_t *sp[ROUND_TAIL];
+        uint32_t on[ROUND_TAIL], len[ROUND_TAIL];
+        resolve_records<BATCH, ROUND_TAIL>(B, lj, ob, on, sp, len);
+        run_records<ROUND_TAIL>(ob, on, sp, dst, src, len, B.long_copy);
+        for (uint32_t r = lo_k + ROUND_TAIL * NT_TAIL + threadIdx.x;; r += ROUND_TAIL * NT_TAIL) {
             if (__ballot(r < hi_k) == 0) break;
-            load_records<BATCH>(B, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
-            run_records(ob, on, sp, dst, src, len, B.long_copy);
+            load_records<BATCH, ROUND_TAIL>(B, min(r, hi_k - 1), NT_TAIL, r < hi_k ? hi_k : 0, ob, on, sp, dst, src, len);
+            run_records<ROUND_TAIL>(ob, on, sp, dst, src, len, B.long_copy);
         }
         __syncthreads();
     }
@@ -1114,10 +1122,19 @@ bool tune_valid(const Tune &t)
            t.xcd_parts >= 1 && t.xcd_parts <= 8;
 }
 
-uint32_t level_wgs(uint64_t records, const Tune &tn)
+uint32_t level_wgs(uint64_t records, uint32_t per_thread, const Tune &tn)
 {
-    const uint64_t per_wg = (uint64_t)NT * ROUND;
+    const uint64_t per_wg = (uint64_t)NT * per_thread;
     return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tn.level_wg_max, (records + per_wg - 1) / per_wg));
+}
+
+template <bool BATCH>
+void launch_level(const Batch &B, uint32_t k, uint64_t cnt, const Tune &tn, hipStream_t st)
+{
+    if (cnt <= (uint64_t)tn.level_wg_max * NT)
+        hipLaunchKernelGGL((k_level<BATCH, 1>), dim3(level_wgs(cnt, 1, tn)), dim3(NT), 0, st, B, k);
+    else
+        hipLaunchKernelGGL((k_level<BATCH, ROUND_LEVEL>), dim3(level_wgs(cnt, ROUND_LEVEL, tn)), dim3(NT), 0, st, B, k);
 }
 
 // Level launches: one per level with records, sized to its count, and the
@@ -1136,9 +1153,9 @@ void launch_levels(const Batch &B, const uint64_t *counts, uint64_t n_seq, const
         const uint64_t cnt = counts ? counts[k] : n_seq;
         if (counts && !cnt) continue;
         if (B.jobs)
-            hipLaunchKernelGGL(k_level<true>, dim3(level_wgs(cnt, tn)), dim3(NT), 0, st, B, k);
+            launch_level<true>(B, k, cnt, tn, st);
         else
-            hipLaunchKernelGGL(k_level<false>, dim3(level_wgs(cnt, tn)), dim3(NT), 0, st, B, k);
+            launch_level<false>(B, k, cnt, tn, st);
     }
     if (tail <= B.max_level) {
         if (B.jobs)
