@@ -66,6 +66,12 @@ def _short(name: str) -> str:
     return m.group(1) if m else name.split("(")[0][:60]
 
 
+def _label(name: str) -> str:
+    """The kernel's name with its template arguments (k_level<false, 1u>)."""
+    m = re.search(r"::(k_\w+(?:<[^>]*>)?)\(", name)
+    return m.group(1) if m else _short(name)
+
+
 def calibration(d: str, counter: str) -> float:
     """Bytes per counter unit: 1 GiB over what the counter read for the copy
     dispatches of 1 GiB (the largest dispatches of the copy run)."""
@@ -160,7 +166,7 @@ def trace(args):
              "## Per-kernel statistics over the run", "",
              "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share of GPU time |", "|---|---|---|---|---|---|"]
     for r in stats:
-        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+        lines.append(f"| {_label(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f}% |")
     starts = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "k_setup"]
     if starts:
@@ -179,9 +185,9 @@ def trace(args):
         for r in seq:
             k = _short(r["Kernel_Name"])
             a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
-            label = k
+            label = _label(r["Kernel_Name"])
             if k == "k_level":
-                label = f"k_level (launch {lvl})"
+                label = f"{label} (launch {lvl})"
                 lvl += 1
             lines.append(f"| {label} | {r['Grid_Size_X']} | {(a - t0) / 1e3:.1f} | {(b - a) / 1e3:.1f} |")
         total = (int(seq[-1]["End_Timestamp"]) - t0) / 1e3
