@@ -233,7 +233,7 @@ int aceapex_plan_get_tuning(const aceapex_plan *plan, aceapex_tuning *tuning);
  * level_wg_max, tail_level_max, long_copy and xcd_parts, each candidate timed
  * with HIP events over reps launches after one warm-up; a candidate is kept
  * when it is at least 1% faster.  The plan keeps the winner, also written to
- * *best when best is not NULL.  Synchronous; runs about 15 * (reps + 1)
+ * *best when best is not NULL.  Synchronous; runs about 16 * (reps + 1)
  * decodes of the batch, each leaving the outputs decoded. */
 int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceapex_tuning *best);
 

@@ -1788,7 +1788,7 @@ int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceap
     };
     // coordinate descent over the knobs, one at a time, from the current schedule
     static const uint32_t wg[] = {512, 1024, 2048, 4096, 8192};
-    static const uint32_t tail[] = {0, 2048, 8192, 32768};
+    static const uint32_t tail[] = {0, 1024, 2048, 8192, 32768};
     static const uint32_t longc[] = {32, 64, 128, 512};
     static const uint32_t parts[] = {1, 2, 4, 8};
     Tune cur = p->tune;
