@@ -145,11 +145,14 @@ def test_doubling_string_long_matches():
     parity(np.frombuffer(x, np.uint8), s, "doubling")
 
 
-@pytest.mark.parametrize("m", [500, 2000, 5000])
+@pytest.mark.parametrize("m", [500, 2000, 5000, 9000])
 def test_level_chains_of_every_histogram_shape(m):
     """m chained 4-byte copies: levels 0..m-1.  500 and 2000 levels take the
     parse shapes with 1024- and 4096-level LDS histograms; 5000 levels go past
-    the largest, so the deepest levels take one global atomic per match."""
+    the largest, so the deepest levels take one global atomic per match.
+    9000 one-match levels all run in the tail workgroup, more of them than the
+    tail keeps slot ranges for in LDS (8192), so the last ones are read from
+    the level table in memory."""
     blocks = [([(4, 4, 0)] + [(0, 4, 4 * i) for i in range(1, m)], 0)]
     n = 4 + 4 * m
     s, want = streamgen.build(blocks, b"abcd", n, block_log2=16, chunk_log2=5)
