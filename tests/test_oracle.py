@@ -128,6 +128,99 @@ def test_w2_chain_crossing_blocks_keeps_dependency():
     assert t[5300] == (5100, 1)
 
 
+def _r2_input():
+    """512-byte blocks.  Block 1 holds the literal run C (700..731).  Block 2
+    holds B = copy of C at 1100, a literal run C' at 1160, B' = copy of C' at
+    1220, then A = copy of C at 1300 and A' = copy of C' at 1420."""
+    rng = np.random.default_rng(4321)
+    x = bytearray(rng.integers(0, 256, 2048, dtype=np.uint8).tobytes())
+    x[1100:1132] = x[700:732]
+    x[1220:1252] = x[1160:1192]
+    x[1300:1332] = x[700:732]
+    x[1420:1452] = x[1160:1192]
+    return bytes(x)
+
+
+@pytest.mark.parametrize("flatten,want", [
+    # no flattening, most-recent tie-break: A and A' take the latest copy
+    (0, {1100: (700, 0), 1220: (1160, 0), 1300: (1100, 1), 1420: (1220, 1)}),
+    # R1: every chain is traced inside block 2; A's trace leaves the block
+    # at 700 (first position outside), the trace of A' ends at the literal C'
+    (1, {1100: (700, 0), 1220: (1160, 0), 1300: (700, 0), 1420: (1160, 0)}),
+    # R2: only chains rooted at a literal of the block are re-pointed: A'
+    # moves to C', A keeps its source B because B's chain leaves the block
+    (2, {1100: (700, 0), 1220: (1160, 0), 1300: (1100, 1), 1420: (1160, 0)}),
+])
+def test_flatten_modes_on_two_chains(flatten, want):
+    """Sec. 3.3 and its limitation: the three flattening readings give three
+    different source sets on one input with a cross-block chain (C -> B -> A)
+    and an in-block literal chain (C' -> B' -> A')."""
+    x = _r2_input()
+    s = oracle.encode(x, hash_bits=16, tiebreak=1, flatten=flatten, block_log2=9)
+    t = {d: (src, lv) for d, src, ln, lv in toks(s) if ln >= 32}
+    assert {d: t[d] for d in want} == want
+    assert oracle.decode(s).tobytes() == x
+
+
+def flattened_from_definition(x, plain_tokens, B, mode, m0=4):
+    """The matches that flattening must produce, recomputed from the
+    unflattened parse by following each byte's chain backwards (Sec. 3.3).
+
+    A byte of a match in block [bs, bs+B) traces its source y: while y lies in
+    the block and was written by a match, y moves to that match's source byte.
+    The trace ends at a literal of the block (the chain is literal-rooted) or
+    at a position before the block.  Mode 1 re-points the byte to where the
+    trace ends; mode 2 re-points it only when the chain is literal-rooted and
+    otherwise keeps its own source.  Each match is cut where the new sources
+    stop being consecutive; pieces shorter than m0 become literals."""
+    src_of = {}
+    for dst, src, ln, _ in plain_tokens:
+        for k in range(ln):
+            src_of[dst + k] = src + k
+    out = []
+    for dst, src, ln, _ in plain_tokens:
+        bs = dst // B * B
+        new = []
+        for k in range(ln):
+            y = src + k
+            while y >= bs and y in src_of:
+                y = src_of[y]
+            rooted = y >= bs
+            new.append(y if (mode == 1 or rooted) else src + k)
+        a = 0
+        while a < ln:
+            b = a + 1
+            while b < ln and new[b] == new[b - 1] + 1:
+                b += 1
+            if b - a >= m0:
+                out.append((dst + a, new[a], b - a))
+            a = b
+    return out
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("seed", range(6))
+def test_flattening_matches_definition(mode, seed):
+    """Both flattening readings equal their definition recomputed from the
+    unflattened parse (most-recent tie-break, no depth limit: the parse then
+    does not depend on levels, so flattening is a pure rewrite of it)."""
+    rng = np.random.default_rng(100 + seed)
+    alpha = [2, 3, 4, 16][seed % 4]
+    n = int(rng.integers(300, 4000))
+    base = rng.integers(0, alpha, n, dtype=np.uint8)
+    for _ in range(n // 40):  # repeats so that chains of copies appear
+        ln = int(rng.integers(4, 40))
+        d = int(rng.integers(ln, n - ln)) if n > 2 * ln else 0
+        s0 = int(rng.integers(0, d - ln + 1)) if d >= ln else 0
+        base[d:d + ln] = base[s0:s0 + ln]
+    x = base.tobytes()
+    bl = [3, 5, 6, 8, 9, 12][seed]
+    o = dict(hash_bits=12, tiebreak=1, block_log2=bl, chunk_log2=2)
+    plain = toks(oracle.encode(x, **o))
+    got = [(d, s_, ln) for d, s_, ln, _ in toks(oracle.encode(x, flatten=mode, **o))]
+    assert got == flattened_from_definition(x, plain, 1 << bl, mode)
+
+
 # ------------------------------------------------------------------ brute force
 
 OPTION_GRID = [
@@ -141,6 +234,8 @@ OPTION_GRID = [
     dict(block_log2=3, chunk_log2=0),
     dict(block_log2=4, flatten=1, tiebreak=1, chunk_log2=1),
     dict(block_log2=3, max_depth=2, chunk_log2=1),
+    dict(block_log2=3, flatten=2, tiebreak=1, chunk_log2=0),
+    dict(block_log2=3, flatten=1, tiebreak=1, chunk_log2=1),
 ]
 
 
@@ -165,6 +260,10 @@ def _check_stream(x, s, opts):
             assert all(lit[y] for y in range(max(src, bs), src + ln))
     if opts.get("max_depth"):
         assert all(lv <= opts["max_depth"] - 1 for *_, lv in t)
+    if opts.get("flatten") and opts.get("tiebreak") == 1 and not opts.get("max_depth"):
+        # R1 / R2: the matches are the definition's rewrite of the unflattened parse
+        plain = toks(oracle.encode(x, **dict(opts, flatten=0)))
+        assert [(d, s_, ln) for d, s_, ln, _ in t] == flattened_from_definition(x, plain, B, opts["flatten"])
     return t
 
 
