@@ -73,7 +73,9 @@ extern "C" {
 #define ACEAPEX_E_CAPACITY -4    /* out_capacity < decoded_bytes                           */
 #define ACEAPEX_E_WORKSPACE -5   /* workspace missing or too small                         */
 #define ACEAPEX_E_UNSUPPORTED -6 /* outside the GPU limits listed above                    */
-#define ACEAPEX_E_TIMEOUT -7     /* a device-side wait hit its spin limit (device status)  */
+#define ACEAPEX_E_TIMEOUT -7     /* reserved for a device-side wait that hits a spin limit; */
+                                 /* no kernel of this version waits on another, so no call  */
+                                 /* returns it                                              */
 #define ACEAPEX_E_HIP -8         /* HIP runtime error, see aceapex_last_hip_error()        */
 #define ACEAPEX_E_NOMEM -9       /* host allocation failed (encoder)                       */
 
@@ -114,9 +116,14 @@ typedef struct {
     int32_t *d_status;      /* device int32 written by the decoder (0 = ok); may be NULL   */
 } aceapex_desc;
 
-/* Parse and check the 64-byte header.  h_len must be >= 64.  Pure host code.
- * Returns ACEAPEX_OK, ACEAPEX_E_INVAL (null pointer or h_len < 64) or
- * ACEAPEX_E_FORMAT. */
+/* Parse and check the 64-byte header.  Blocks carry no context of their own
+ * (Sec. 3.1: any block decodes once the bytes its absolute sources name
+ * exist), so the header alone fixes the decode's shape: decoded size, block
+ * count and size, and the deepest dependency level (Sec. 7.1) that sets the
+ * number of wavefronts.  h_len must be >= 64.  Pure host code.  Returns
+ * ACEAPEX_OK, ACEAPEX_E_INVAL (null pointer or h_len < 64) or
+ * ACEAPEX_E_FORMAT (bad magic or version, unknown flags, levels absent, or
+ * fields that contradict each other). */
 int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info);
 
 /* Copy the stream's level table (the number of matches at each dependency
@@ -128,14 +135,19 @@ int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info)
 int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *counts, uint32_t n);
 
 /* Device workspace, in bytes, that aceapex_decode_many needs for these n
- * descriptors (n = 1 for aceapex_decode).  Pure host code; returns 0 when a
- * descriptor's info is inconsistent. */
+ * descriptors (n = 1 for aceapex_decode): per chunk a 48-byte descriptor of
+ * its slices of the Sec. 3.2 streams, per level of Sec. 7.1 three slot
+ * counters, and 12 bytes per match for the level-grouped match records.  Pure
+ * host code; returns 0 when a descriptor's info is inconsistent. */
 size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n);
 
 /* Decode one stream into d_out (Sec. 3.2, Sec. 7.1).  d_workspace must hold
  * aceapex_workspace_bytes() for this stream, 256-byte aligned; its contents
  * on entry do not matter.  d_status may be NULL (the status is then kept in
- * the workspace).  Asynchronous on hip_stream. */
+ * the workspace).  Asynchronous on hip_stream.  A host level table
+ * (stream->h_levels) whose counts do not add up to n_seq is refused with
+ * ACEAPEX_E_FORMAT; one that differs from the stream's own level table makes
+ * the device status ACEAPEX_E_CORRUPT. */
 int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capacity,
                    void *d_workspace, size_t ws_bytes, int32_t *d_status, void *hip_stream);
 
@@ -148,11 +160,14 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
  * overflow the 32-bit indexes of one sequence, runs as several consecutive
  * sequences.  Without the tables the streams are decoded one after the other.
  * Returns the first synchronous error; per-stream device errors go to each
- * d_status. */
+ * d_status.  Host level tables are checked as in aceapex_decode: a table
+ * whose counts do not add up to n_seq is refused (ACEAPEX_E_FORMAT), one that
+ * differs from the stream's own table fails that stream (ACEAPEX_E_CORRUPT). */
 int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace,
                         size_t ws_bytes, void *hip_stream);
 
-/* Static English text for an error code. */
+/* Static English text for an error code (ACEAPEX_E_* above; "unknown error"
+ * for any other value).  Pure host code. */
 const char *aceapex_strerror(int code);
 
 /* The last hipError_t seen by a call that returned ACEAPEX_E_HIP (0 if none). */
@@ -257,8 +272,8 @@ typedef struct {
     uint32_t tiebreak;    /* among candidates of equal length: 0 lowest level, 1 most recent      */
     uint32_t chunk_log2;  /* sequences per chunk-index entry (10)                                 */
     uint32_t threads;     /* host threads, 0 = all                                                */
-    uint32_t verbose;     /* nonzero: the sequential depth-limited parse reports its progress on  */
-                          /* stderr every 64 blocks                                               */
+    uint32_t verbose;     /* nonzero: the in-order pass reports its progress on stderr every 64  */
+                          /* blocks                                                               */
 } aceapex_enc_opts;
 
 /* Fill *o with the defaults above.  Pure host code. */

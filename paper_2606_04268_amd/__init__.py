@@ -95,17 +95,33 @@ def _stream_handle(stream):
     return st.cuda_stream
 
 
+def _used_on(stream, tensors):
+    """Mark tensors allocated here as in use by ``stream`` when it is not the
+    current stream, so that the caching allocator does not hand their memory
+    to another tensor while the decode enqueued there may still use it."""
+    torch = _torch()
+    if stream is None or stream == torch.cuda.current_stream(stream.device):
+        return
+    for t in tensors:
+        t.record_stream(stream)
+
+
 def decode(ds: DeviceStream, out=None, workspace=None, status=None, stream=None):
     """Enqueue a decode of ``ds``; returns (out, status) tensors.  Asynchronous."""
     torch = _torch()
     dev = ds.comp.device
+    mine = []  # tensors allocated here
     if out is None:
         out = torch.empty(max(ds.n, 1), dtype=torch.uint8, device=dev)
+        mine.append(out)
     need = workspace_bytes([ds])
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        mine.append(workspace)
     if status is None:
         status = torch.empty(1, dtype=torch.int32, device=dev)
+        mine.append(status)
+    _used_on(stream, mine)
     rc = _abi.decode(ds.abi(), out.data_ptr(), out.numel(), workspace.data_ptr(), workspace.numel(),
                      status.data_ptr(), _stream_handle(stream))
     if rc:
@@ -117,15 +133,20 @@ def decode_many(streams, outs=None, workspace=None, statuses=None, stream=None):
     """Enqueue one batched decode of many streams; returns (outs, statuses)."""
     torch = _torch()
     dev = streams[0].comp.device if streams else "cuda"
+    mine = []  # tensors allocated here
     if outs is None:
         outs = [torch.empty(max(s.n, 1), dtype=torch.uint8, device=dev) for s in streams]
+        mine += outs
     if statuses is None:
         statuses = torch.empty(max(len(streams), 1), dtype=torch.int32, device=dev)
+        mine.append(statuses)
     descs = [_abi.Desc(s.abi(), o.data_ptr(), o.numel(), statuses.data_ptr() + 4 * i)
              for i, (s, o) in enumerate(zip(streams, outs))]
     need = _abi.workspace_bytes(descs) if descs else 0
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        mine.append(workspace)
+    _used_on(stream, mine)
     rc = _abi.decode_many(descs, workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
     if rc:
         raise AceapexError(rc, "decode_many")

@@ -25,8 +25,9 @@
 //   k_seal    (batches) record slots a corrupt stream left unfilled get length 0.
 //   k_level   one launch per level k (Sec. 7.1): the copies of level k read
 //             only bytes written by literals or by lower levels and are
-//             independent of each other, so every thread simply runs four
-//             records at a time.  Launch boundaries order the levels.
+//             independent of each other, so every thread runs one record per
+//             round (two on levels larger than the launch).  Launch
+//             boundaries order the levels.
 //   k_tail    the deep levels that hold few matches run in a single workgroup,
 //             level after level, separated by workgroup barriers: one CU, so
 //             no cache maintenance between levels.
@@ -118,7 +119,23 @@ struct Batch {
     uint32_t n_seq;             // matches over the batch
     uint32_t long_copy;         // matches longer than this are copied by a whole wave
     uint32_t xcd_parts;         // k_level: contiguous parts of a level's records (1..8)
+    uint32_t has_sig;           // single stream: the host scheduled the levels from a table
+    uint64_t level_sig;         //   whose signature (level_signature) is this
 };
+
+// Signature of a level table: the sum over levels k of a 64-bit mix of
+// (k, count_k) (the SplitMix64 finalizer).  The single-stream decode sizes its
+// level launches from the caller's host copy of the table and the device
+// builds the record slots from the stream's own table; k_setup compares the
+// two signatures so that a stale host table fails the decode instead of
+// skipping a level.
+__host__ __device__ __forceinline__ uint64_t level_mix(uint32_t k, uint32_t c)
+{
+    uint64_t z = (((uint64_t)k << 32) | c) + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
 
 __device__ __forceinline__ const Job &job_of(const Batch &B, uint32_t s) { return B.jobs ? B.jobs[s] : B.one; }
 
@@ -472,14 +489,14 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
     if (!B.jobs && blockIdx.x == 0) {
         // single stream: its level table -> record slots of every level
         const Job &j = B.one;
-        if (t == 0) *j.status = 0;
         const uint64_t lvl_tab = HDR + 16ull * (j.n_blocks + 1);
-        uint64_t carry = 0;
+        uint64_t carry = 0, sig = 0;
         for (uint32_t s = 0; s <= j.max_level; s += NT) {
             const uint32_t i = s + t;
             const uint32_t c = i <= j.max_level ? ld32(j.comp + lvl_tab + 4ull * i) : 0;
-            uint64_t tot;
+            uint64_t tot, mixed;
             const uint64_t ex = wg_excl_scan64(c, tmp, tot);
+            (void)wg_excl_scan64(i <= j.max_level ? level_mix(i, c) : 0, tmp, mixed);
             if (i <= j.max_level) {
                 const uint32_t lo = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
                 B.rec_lo[i] = lo;
@@ -487,14 +504,28 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
                 B.rec_hi[i] = (uint32_t)min(carry + ex + c, (uint64_t)j.n_seq);
             }
             carry += tot;
+            sig += mixed;
         }
-        if (t == 0 && carry != j.n_seq) fail(j, ACEAPEX_E_CORRUPT);  // every match counted exactly once
+        // every match counted exactly once, and the levels the host scheduled are these
+        if (t == 0)
+            *j.status = (carry != j.n_seq || (B.has_sig && sig != B.level_sig)) ? ACEAPEX_E_CORRUPT : 0;
     }
     if (B.jobs && blockIdx.x < B.n_jobs) {
-        // batch: clear this stream's status and level cursors (slots were laid out on the host)
+        // batch: this stream's level cursors (slots were laid out on the host
+        // from its host level table, which must equal the stream's own), then
+        // its status
         const Job &j = B.jobs[blockIdx.x];
-        if (t == 0) *j.status = 0;
-        for (uint32_t i = t; i <= j.max_level; i += NT) B.cursor[j.lv0 + i] = B.rec_lo[j.lv0 + i];
+        const uint64_t lvl_tab = HDR + 16ull * (j.n_blocks + 1);
+        if (t == 0) ok_blk = 1;
+        __syncthreads();
+        for (uint32_t i = t; i <= j.max_level; i += NT) {
+            const uint32_t lo = B.rec_lo[j.lv0 + i];
+            B.cursor[j.lv0 + i] = lo;
+            if (ld32(j.comp + lvl_tab + 4ull * i) != B.rec_hi[j.lv0 + i] - lo) ok_blk = 0;
+        }
+        __syncthreads();
+        if (t == 0) *j.status = ok_blk ? 0 : ACEAPEX_E_CORRUPT;
+        __syncthreads();
     }
 
     for (uint32_t gb = blockIdx.x; gb < B.n_blocks; gb += gridDim.x) {
@@ -1140,8 +1171,8 @@ void launch_level(const Batch &B, uint32_t k, uint64_t cnt, const Tune &tn, hipS
 // Level launches: one per level with records, sized to its count, and the
 // deep levels that hold few matches together in the tail workgroup.  counts
 // is null when the host does not know them (full-size launch per level).
-void launch_levels(const Batch &B, const uint64_t *counts, uint64_t n_seq, const Tune &tn, hipStream_t st,
-                   bool timed)
+template <typename C>
+void launch_levels(const Batch &B, const C *counts, uint64_t n_seq, const Tune &tn, hipStream_t st, bool timed)
 {
     PhaseScope ps(PH_LEVELS, st, timed);
     uint32_t tail = B.max_level + 1;
@@ -1223,11 +1254,11 @@ struct Group {
     bool single = false;
 };
 
-void build_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, Group &g)
+// The kernel arguments of a single-stream decode (no host allocation).
+void single_batch(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, Batch &B)
 {
     const aceapex_info &in = s.info;
     const WsLayout w = ws_single(in);
-    Batch &B = g.B;
     memset(&B, 0, sizeof B);
     B.one = make_job(s, d_out, d_status ? d_status : (int32_t *)(ws + w.status), (ChunkDesc *)(ws + w.chunks),
                      ws + w.blk_ok, 0, 0, 0);
@@ -1240,6 +1271,16 @@ void build_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     B.n_chunks = in.n_chunks;
     B.max_level = in.max_level;
     B.n_seq = in.n_seq;
+    if (s.h_levels) {
+        B.has_sig = 1;
+        for (uint32_t k = 0; k <= in.max_level; k++) B.level_sig += level_mix(k, s.h_levels[k]);
+    }
+}
+
+void build_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, Group &g)
+{
+    const aceapex_info &in = s.info;
+    single_batch(s, d_out, ws, d_status, g.B);
     g.tot.clear();
     if (s.h_levels) g.tot.assign(s.h_levels, s.h_levels + in.max_level + 1);
     g.n_blocks = in.n_blocks;
@@ -1377,29 +1418,39 @@ void build_group(const aceapex_desc *d, uint32_t n, uint8_t *ws, uint8_t *h, Gro
     g.n = n;
 }
 
+// The kernels of a single-stream decode; counts (matches per level) may be
+// null.
+template <typename C>
+void enqueue_single(Batch B, const C *counts, const Tune &tn, hipStream_t st, bool timed)
+{
+    B.long_copy = tn.long_copy;
+    B.xcd_parts = tn.xcd_parts;
+    {
+        PhaseScope ps(PH_SETUP, st, timed);
+        hipLaunchKernelGGL(k_setup, dim3(std::max<uint32_t>(1, std::min<uint32_t>(B.n_blocks, 65535))), dim3(NT), 0,
+                           st, B);
+    }
+    if (B.n_blocks) {
+        {
+            PhaseScope ps(PH_PARSE, st, timed);
+            launch_parse<false>(B, B.n_chunks, st);
+        }
+        if (B.n_seq) launch_levels(B, counts, B.n_seq, tn, st, timed);
+    }
+}
+
 // The kernels of one group (nothing else: no copy, no allocation, no
 // memset), so that the sequence can be captured into a graph.
 void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
 {
+    const uint64_t *counts = g.tot.empty() ? nullptr : g.tot.data();
+    if (g.single) {
+        enqueue_single(g.B, counts, tn, st, timed);
+        return;
+    }
     Batch B = g.B;
     B.long_copy = tn.long_copy;
     B.xcd_parts = tn.xcd_parts;
-    const uint64_t *counts = g.tot.empty() ? nullptr : g.tot.data();
-    if (g.single) {
-        {
-            PhaseScope ps(PH_SETUP, st, timed);
-            hipLaunchKernelGGL(k_setup, dim3((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g.n_blocks, 65535))),
-                               dim3(NT), 0, st, B);
-        }
-        if (g.n_blocks) {
-            {
-                PhaseScope ps(PH_PARSE, st, timed);
-                launch_parse<false>(B, (uint32_t)g.n_chunks, st);
-            }
-            if (g.n_seq) launch_levels(B, counts, g.n_seq, tn, st, timed);
-        }
-        return;
-    }
     {
         PhaseScope ps(PH_SETUP, st, timed);
         hipLaunchKernelGGL(k_map, dim3(g.n), dim3(NT), 0, st, B);
@@ -1456,6 +1507,11 @@ int check_stream_args(const aceapex_stream *s, const void *d_out, uint64_t cap)
     if (rc) return rc;
     if (s->info.decoded_bytes && !d_out) return ACEAPEX_E_INVAL;
     if (cap < s->info.decoded_bytes) return ACEAPEX_E_CAPACITY;
+    if (s->h_levels) {  // a host level table must count every match once (its slots are laid out from it)
+        uint64_t sum = 0;
+        for (uint32_t k = 0; k <= s->info.max_level; k++) sum += s->h_levels[k];
+        if (sum != s->info.n_seq) return ACEAPEX_E_FORMAT;
+    }
     return ACEAPEX_OK;
 }
 

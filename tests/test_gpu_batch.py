@@ -106,3 +106,74 @@ def test_corrupt_streams_do_not_disturb_their_batch():
             else:
                 assert st[i] == 0
                 assert np.array_equal(got, x)
+
+
+def test_more_streams_than_one_launch_sequence():
+    """2,100 streams: more than one launch sequence holds (2,048), so the
+    batch runs as two sequences with the workspace split between them, in
+    aceapex_decode_many and in a plan (direct launches and graph replay)."""
+    import torch
+
+    import paper_2606_04268_amd as ax
+
+    rng = np.random.default_rng(2100)
+    pairs = []
+    for i in range(2100):
+        n = int(np.exp(rng.uniform(np.log(64), np.log(12_000))))
+        x = synth.make(["markov", "fastq", "random", "wiki"][i % 4], n, 77_000 + i)
+        opts = dict(block_log2=int(rng.choice([8, 10, 12])), flatten=int(rng.integers(0, 3)),
+                    max_depth=int(rng.choice([0, 0, 2])), chunk_log2=int(rng.choice([2, 5, 10])), hash_bits=12)
+        pairs.append((x, oracle.encode(x, **opts)))
+    for x, s in pairs:
+        assert np.array_equal(oracle.decode(s), x)
+    say(f"[gpu] decode_many {len(pairs)} streams (two launch sequences)")
+    res, st = run_batch(pairs)
+    assert (st == 0).all()
+    for (x, _), got in zip(pairs, res):
+        assert np.array_equal(got, x)
+
+    dss = [ax.to_device(s) for _, s in pairs]
+    outs = [torch.full((max(d.n, 1),), POISON, dtype=torch.uint8, device="cuda") for d in dss]
+    plan = ax.Plan(dss, outs=outs)
+    try:
+        for graph in (False, True, True):
+            say(f"[gpu] plan of {len(dss)} streams, graph={graph}")
+            for o in outs:
+                o.fill_(POISON)
+            plan.statuses.fill_(12345)
+            plan.launch(graph=graph)
+            torch.cuda.synchronize()
+            ax.check_status(plan.statuses)
+            for (x, _), o in zip(pairs, outs):
+                assert np.array_equal(o[:x.size].cpu().numpy(), x)
+    finally:
+        plan.close()
+
+
+def test_decode_on_a_side_stream_without_buffers():
+    """decode() and decode_many() allocate their own output, status and
+    workspace when none is given; enqueued on a stream that is not the
+    current one, those tensors must stay reserved for that stream until the
+    decode there has run."""
+    import torch
+
+    import paper_2606_04268_amd as ax
+
+    pairs = mixed_streams(6, 31)
+    side = torch.cuda.Stream()
+    dss = [ax.to_device(s) for _, s in pairs]
+    torch.cuda.synchronize()
+    results = []
+    for d in dss:
+        results.append(ax.decode(d, stream=side))
+    outs, sts = ax.decode_many(dss, stream=side)
+    # allocations on the current stream meanwhile must not reuse those buffers
+    junk = [torch.full((1 << 20,), 7, dtype=torch.uint8, device="cuda") for _ in range(16)]
+    side.synchronize()
+    torch.cuda.synchronize()
+    del junk
+    for (x, _), (o, st), o2 in zip(pairs, results, outs):
+        assert int(st.item()) == 0
+        assert np.array_equal(o[:x.size].cpu().numpy(), x)
+        assert np.array_equal(o2[:x.size].cpu().numpy(), x)
+    assert (sts.cpu().numpy() == 0).all()

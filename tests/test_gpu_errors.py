@@ -1,0 +1,216 @@
+"""Corrupt single streams through aceapex_decode: each must end with device
+status ACEAPEX_E_CORRUPT (-3) -- or be refused on the host -- and never write
+outside the output buffer.  Every stream is built from hand-written token
+lists (tests/streamgen.py) and then damaged at one known place, so each case
+names the check it exercises."""
+import numpy as np
+import pytest
+
+import oracle
+import streamgen
+from gpu_util import GUARD, POISON, gpu_decode, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+BL, CK = 10, 3  # 1 KiB blocks, 8 sequences per chunk
+
+
+def _base(seed=3, n=6000):
+    rng = np.random.default_rng(seed)
+    blocks, lits = streamgen.random_tokens(rng, n, BL, max_len=60)
+    return blocks, lits, n
+
+
+def _sections(s, b):
+    """Byte offsets of block b's sections in stream s."""
+    h = oracle.header_fields(s)
+    at = int.from_bytes(s[64 + 16 * b:72 + 16 * b].tobytes(), "little")
+    hdr = [int.from_bytes(s[at + 4 * i:at + 4 * i + 4].tobytes(), "little") for i in range(8)]
+    ns, nl, nc, _, cmdb, lenb, lvlb, _ = hdr
+    pad = lambda v: (v + 15) // 16 * 16
+    off = at + 32 + 32 * nc
+    cmd = off + pad(4 * ns)
+    ln = cmd + pad(cmdb)
+    lvl = ln + pad(lenb)
+    lit = lvl + pad(lvlb)
+    return dict(at=at, chunks=at + 32, n_chunks=nc, n_seq=ns, off=off, cmd=cmd, cmd_bytes=cmdb, len=ln,
+                len_bytes=lenb, lvl=lvl, lvl_bytes=lvlb, lit=lit, n_lit=nl, max_level=h["max_level"])
+
+
+def _expect_corrupt(s, label):
+    say(f"[gpu] corrupt stream: {label}")
+    _, status = gpu_decode(s)  # checks both guard bands
+    assert status == -3, f"{label}: status {status}"
+
+
+def _valid():
+    blocks, lits, n = _base()
+    s, want = streamgen.build(blocks, lits, n, block_log2=BL, chunk_log2=CK)
+    assert oracle.decode(s).tobytes() == want
+    return blocks, lits, n, s
+
+
+def _set32(s, at, v):
+    s[at:at + 4] = np.frombuffer(int(v).to_bytes(4, "little"), np.uint8)
+
+
+def test_valid_base_stream_decodes():
+    _, _, _, s = _valid()
+    got, status = gpu_decode(s)
+    assert status == 0 and np.array_equal(got, oracle.decode(s))
+
+
+def test_source_overlapping_its_destination():
+    """src + len > dst (Sec. 3.1: a source must be final before its copy)."""
+    blocks, lits, n, s = _valid()
+    b = 2
+    seqs, _ = blocks[b]
+    p = b << BL
+    r, m, _src = seqs[0]
+    dst = p + r
+    sec = _sections(s, b)
+    _set32(s, sec["off"], dst - m + 1)
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(s)
+    _expect_corrupt(s, "source overlaps destination")
+
+
+def test_source_past_the_output():
+    blocks, lits, n, s = _valid()
+    sec = _sections(s, 3)
+    _set32(s, sec["off"] + 4, 0xFFFFFF00)
+    _expect_corrupt(s, "source beyond the output")
+
+
+def test_truncated_varint():
+    """The last byte of a block's cmd[] carries a continuation bit: the
+    trailing run's LEB128 value never ends."""
+    _, _, _, s = _valid()
+    sec = _sections(s, 1)
+    s[sec["cmd"] + sec["cmd_bytes"] - 1] |= 0x80
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(s)
+    _expect_corrupt(s, "truncated cmd varint")
+
+
+def test_level_above_max_level():
+    blocks, lits, n = _base()
+    _, exact = streamgen.execute(blocks, lits, n, BL)
+    top = max(exact)
+    hist = [0] * (top + 1)
+    for lv in exact:
+        hist[lv] += 1
+    levels = list(exact)
+    levels[len(levels) // 2] = top + 1  # lvl[] holds top + 1; header and level table say top
+    s, _ = streamgen.build(blocks, lits, n, block_log2=BL, chunk_log2=CK, levels=levels, max_level=top,
+                           level_counts=hist)
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(s)
+    _expect_corrupt(s, "a level above max_level")
+
+
+def test_level_table_off_by_one():
+    """The stream's level table moves one match from level 0 to level 1
+    (counts still add up to n_seq): the parse finds more level-0 matches than
+    the table announced."""
+    blocks, lits, n = _base()
+    _, exact = streamgen.execute(blocks, lits, n, BL)
+    hist = [0] * (max(exact) + 1)
+    for lv in exact:
+        hist[lv] += 1
+    assert len(hist) > 1 and hist[0] > 0
+    hist[0] -= 1
+    hist[1] += 1
+    s, _ = streamgen.build(blocks, lits, n, block_log2=BL, chunk_log2=CK, level_counts=hist)
+    _expect_corrupt(s, "level table off by one")
+
+
+def test_chunk_entry_past_its_section():
+    _, _, _, s = _valid()
+    sec = _sections(s, 1)
+    assert sec["n_chunks"] > 1
+    _set32(s, sec["chunks"] + 32, sec["cmd_bytes"] + 64)  # chunk 1's cmd offset beyond cmd[]
+    _expect_corrupt(s, "chunk entry past its section")
+
+
+def test_literal_count_mismatch():
+    _, _, _, s = _valid()
+    sec = _sections(s, 2)
+    _set32(s, sec["at"] + 4, sec["n_lit"] + 1)
+    _expect_corrupt(s, "n_lit one too large")
+
+
+def test_misaligned_block_offset():
+    _, _, _, s = _valid()
+    at = 64 + 16 * 2
+    v = int.from_bytes(s[at:at + 8].tobytes(), "little") + 8
+    s[at:at + 8] = np.frombuffer(v.to_bytes(8, "little"), np.uint8)
+    _expect_corrupt(s, "block offset not 16-aligned")
+
+
+def test_host_level_table_checked():
+    """The caller's host copy of the level table: counts that do not add up to
+    n_seq are refused on the host (E_FORMAT); counts that add up but differ
+    from the stream's own table fail the decode on the device."""
+    import ctypes
+
+    import torch
+
+    import paper_2606_04268_amd as ax
+    from paper_2606_04268_amd import _abi
+
+    _, _, _, s = _valid()
+    ds = ax.to_device(s)
+    nl = ds.info.max_level + 1
+    assert nl > 1
+    good = [int(ds.levels[k]) for k in range(nl)]
+    buf = torch.full((ds.n + 2 * GUARD,), POISON, dtype=torch.uint8, device="cuda")
+    out = buf[GUARD:GUARD + ds.n]
+    ws = torch.empty(ax.workspace_bytes([ds]), dtype=torch.uint8, device="cuda")
+    st = torch.full((1,), 12345, dtype=torch.int32, device="cuda")
+    hs = torch.cuda.current_stream().cuda_stream
+
+    short = list(good)
+    short[0] -= 1
+    tab = (ctypes.c_uint32 * nl)(*short)
+    rc = _abi.decode(_abi.Stream(ds.comp.data_ptr(), ds.info, tab), out.data_ptr(), ds.n, ws.data_ptr(),
+                     ws.numel(), st.data_ptr(), hs)
+    assert rc == _abi.E_FORMAT
+    desc = _abi.Desc(_abi.Stream(ds.comp.data_ptr(), ds.info, tab), out.data_ptr(), ds.n, st.data_ptr())
+    assert _abi.decode_many([desc], ws.data_ptr(), ws.numel(), hs) == _abi.E_FORMAT
+
+    moved = list(good)
+    moved[0] -= 1
+    moved[1] += 1
+    tab = (ctypes.c_uint32 * nl)(*moved)
+    rc = _abi.decode(_abi.Stream(ds.comp.data_ptr(), ds.info, tab), out.data_ptr(), ds.n, ws.data_ptr(),
+                     ws.numel(), st.data_ptr(), hs)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(st.item()) == -3
+    h = buf.cpu().numpy()
+    assert (h[:GUARD] == POISON).all() and (h[GUARD + ds.n:] == POISON).all()
+    # the same table in a batch of two: the stream with the stale table fails, the other decodes
+    ds2 = ax.to_device(s)
+    buf2 = torch.full((ds.n + 2 * GUARD,), POISON, dtype=torch.uint8, device="cuda")
+    out2 = buf2[GUARD:GUARD + ds.n]
+    sts = torch.full((2,), 12345, dtype=torch.int32, device="cuda")
+    descs = [_abi.Desc(_abi.Stream(ds.comp.data_ptr(), ds.info, tab), out.data_ptr(), ds.n, sts.data_ptr()),
+             _abi.Desc(ds2.abi(), out2.data_ptr(), ds.n, sts.data_ptr() + 4)]
+    wsb = torch.empty(_abi.workspace_bytes(descs), dtype=torch.uint8, device="cuda")
+    assert _abi.decode_many(descs, wsb.data_ptr(), wsb.numel(), hs) == 0
+    torch.cuda.synchronize()
+    assert sts.cpu().tolist() == [-3, 0]
+    assert np.array_equal(out2.cpu().numpy(), oracle.decode(s))
+    for b in (buf, buf2):
+        h = b.cpu().numpy()
+        assert (h[:GUARD] == POISON).all() and (h[GUARD + ds.n:] == POISON).all()
