@@ -19,8 +19,15 @@
 //      applies flattening and fixes every level, since a block's levels
 //      depend on the final levels of all earlier blocks.
 //   4. blocks are serialized in parallel and concatenated.
-// With a depth limit the candidate lengths depend on levels, and the parse
-// runs block after block on one thread.
+// With a depth limit (Sec. 7.4) a candidate's usable length is cut where its
+// source reaches a byte of level > max_depth - 2, which depends on levels.
+// Where the level-independent parse picks a match whose level stays within
+// the limit, none of its tied candidates is cut, so the limited greedy parse
+// makes the same choice; the in-order pass therefore follows the parallel
+// parse and walks the hash chain with cut lengths itself only where the
+// chosen match would be too deep, and at the positions after it until the
+// two parses meet again (a position the parallel parse decided at: a match
+// start or a literal).
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -47,11 +54,19 @@ struct Piece {
 struct Found {               // one match of the level-independent parse
     uint32_t dst, len;
     uint32_t tie0, nties;    // tied candidates in BlockParse::ties
+    uint32_t alt0, nalts;    // with a depth limit: the longest candidates in BlockParse::alts
 };
+
+struct Alt {                 // a candidate source and its match length
+    uint32_t src, len;
+};
+
+constexpr uint32_t ALTS = 8;  // candidates kept per match for the depth-limited pass
 
 struct BlockParse {
     std::vector<Found> found;
     std::vector<uint32_t> ties;
+    std::vector<Alt> alts;
     std::vector<Piece> pieces;   // final matches of the block
     std::vector<uint8_t> bytes;  // serialized payload
     std::vector<uint32_t> per_level;  // matches of the block at each level
@@ -84,8 +99,8 @@ private:
     }
 
     void build_links();
-    void parse_free(uint64_t b);          // no depth limit
-    void parse_limited(uint64_t b);       // depth limit, needs final levels of earlier bytes
+    void parse_free(uint64_t b);          // level-independent parse: every candidate of the longest length
+    void resolve_limited(uint64_t b);     // depth limit, needs final levels of earlier bytes
     void resolve(uint64_t b);
     void flatten(uint64_t b);
     void relevel(uint64_t b);
@@ -131,17 +146,21 @@ void Encoder::parse_free(uint64_t b)
     BlockParse &bp = blk_[b];
     const uint64_t bs = b * B_, be = std::min(n_, bs + B_);
     const uint64_t m0 = o_.min_match;
+    const bool keep_alts = o_.max_depth != 0;
+    Alt cand[64];
     uint64_t p = bs;
     while (p < be) {
         uint64_t best = 0;
-        uint32_t t0 = (uint32_t)bp.ties.size(), nt = 0;
+        uint32_t t0 = (uint32_t)bp.ties.size(), nt = 0, nc = 0;
         if (p + m0 <= be && p + 4 <= n_) {
             uint32_t s = link_[p];
             for (uint32_t step = 0; s != NIL && step < o_.chain_depth; step++, s = link_[s]) {
                 uint64_t cap = std::min(be - p, p - s);
-                if (cap < m0 || cap < best) continue;
+                if (cap < m0 || (!keep_alts && cap < best)) continue;
                 uint64_t l = common_prefix(s, p, cap);
-                if (l < m0 || l < best) continue;
+                if (l < m0) continue;
+                if (keep_alts && nc < 64) cand[nc++] = {s, (uint32_t)l};
+                if (l < best) continue;
                 if (l > best) {
                     best = l;
                     bp.ties.resize(t0);
@@ -152,7 +171,13 @@ void Encoder::parse_free(uint64_t b)
             }
         }
         if (best >= m0) {
-            bp.found.push_back({(uint32_t)p, (uint32_t)best, t0, nt});
+            uint32_t a0 = (uint32_t)bp.alts.size(), na = 0;
+            if (keep_alts) {  // the ALTS longest candidates, most recent first among equal lengths
+                std::stable_sort(cand, cand + nc, [](const Alt &a, const Alt &b) { return a.len > b.len; });
+                na = std::min<uint32_t>(nc, ALTS);
+                bp.alts.insert(bp.alts.end(), cand, cand + na);
+            }
+            bp.found.push_back({(uint32_t)p, (uint32_t)best, t0, nt, a0, na});
             p += best;
         } else {
             bp.ties.resize(t0);
@@ -161,46 +186,78 @@ void Encoder::parse_free(uint64_t b)
     }
 }
 
-// The same greedy parse, but a candidate's length is cut where its source
-// reaches a byte of level > max_depth - 2, so that no match exceeds level
-// max_depth - 1 (Sec. 7.4).  Resolves the level of every match on the way.
-void Encoder::parse_limited(uint64_t b)
+// The depth-limited parse of block b (Sec. 7.4: every match level at most
+// max_depth - 1), from the level-independent one.  A match of that parse
+// whose level stays within the limit is kept whole (its least deep tied
+// candidate, as without the limit).  A deeper one is re-cut over its own
+// span [p, p + len): at each position q of the span, the kept candidates
+// shifted by q - p are still copies of the bytes at q; each is cut where its
+// source reaches a byte of level > max_depth - 2, the longest cut piece (the
+// least deep among equal lengths, the most recent among equal levels) of at
+// least min_match bytes is taken, else q becomes a literal.  The pieces end
+// inside the span, so the pass meets the level-independent parse again at
+// p + len.
+void Encoder::resolve_limited(uint64_t b)
 {
     BlockParse &bp = blk_[b];
     const uint64_t bs = b * B_, be = std::min(n_, bs + B_);
     const uint64_t m0 = o_.min_match;
-    const int32_t lim = (int32_t)o_.max_depth - 2;
-    uint64_t p = bs;
-    while (p < be) {
-        uint64_t best = 0, best_src = 0;
-        int32_t best_lvl = 0;
-        if (p + m0 <= be && p + 4 <= n_) {
-            uint32_t s = link_[p];
-            for (uint32_t step = 0; s != NIL && step < o_.chain_depth; step++, s = link_[s]) {
-                uint64_t cap = std::min(be - p, p - s);
-                if (cap < m0 || cap < best) continue;
-                uint64_t l = common_prefix(s, p, cap);
-                uint64_t ok = 0;
-                while (ok < l && wlev_[s + ok] <= lim) ok++;
-                l = ok;
-                if (l < m0 || l < best) continue;
-                int32_t lv = level_over(s, l);
-                if (l > best || (o_.tiebreak == 0 && lv < best_lvl)) {
-                    best = l;
-                    best_src = s;
-                    best_lvl = lv;
-                }
+    const int32_t top = (int32_t)o_.max_depth - 1, lim = top - 1;
+    bp.pieces.clear();
+    bp.pieces.reserve(bp.found.size());
+    uint64_t cur = bs;
+    for (const Found &f : bp.found) {
+        for (uint64_t q = cur; q < f.dst; q++) wlev_[q] = -1;
+        uint32_t src = bp.ties[f.tie0];
+        int32_t lv = level_over(src, f.len);
+        if (o_.tiebreak == 0) {
+            for (uint32_t k = 1; k < f.nties && lv > 0; k++) {
+                const uint32_t s2 = bp.ties[f.tie0 + k];
+                const int32_t l2 = level_over(s2, f.len);
+                if (l2 < lv) { lv = l2; src = s2; }
             }
         }
-        if (best >= m0) {
-            bp.pieces.push_back({(uint32_t)p, (uint32_t)best_src, (uint32_t)best, best_lvl});
-            std::fill(wlev_.begin() + p, wlev_.begin() + p + best, best_lvl);
-            p += best;
-        } else {
-            wlev_[p] = -1;
-            p++;
+        const uint64_t end = (uint64_t)f.dst + f.len;
+        if (lv <= top) {
+            bp.pieces.push_back({f.dst, src, f.len, lv});
+            std::fill(wlev_.begin() + f.dst, wlev_.begin() + end, lv);
+            cur = end;
+            continue;
         }
+        const Alt *alt = bp.alts.data() + f.alt0;
+        for (uint64_t q = f.dst; q < end;) {
+            const uint64_t d = q - f.dst;
+            uint64_t best = 0, best_src = 0;
+            int32_t best_lvl = 0;
+            for (uint32_t k = 0; k < f.nalts; k++) {
+                if (alt[k].len < d + m0 || alt[k].len - d < best) continue;
+                const uint64_t s = alt[k].src + d, room = alt[k].len - d;
+                const int32_t *w = wlev_.data() + s;
+                uint64_t l = 0;
+                while (l < room && w[l] <= lim) l++;
+                if (l < m0 || l < best) continue;
+                const int32_t lv2 = level_over(s, l);
+                if (l > best || (o_.tiebreak == 0 && lv2 < best_lvl)) {
+                    best = l;
+                    best_src = s;
+                    best_lvl = lv2;
+                }
+            }
+            if (best >= m0) {
+                bp.pieces.push_back({(uint32_t)q, (uint32_t)best_src, (uint32_t)best, best_lvl});
+                std::fill(wlev_.begin() + q, wlev_.begin() + q + best, best_lvl);
+                q += best;
+            } else {
+                wlev_[q] = -1;
+                q++;
+            }
+        }
+        cur = end;
     }
+    for (uint64_t q = cur; q < be; q++) wlev_[q] = -1;
+    std::vector<Found>().swap(bp.found);
+    std::vector<uint32_t>().swap(bp.ties);
+    std::vector<Alt>().swap(bp.alts);
 }
 
 void Encoder::resolve(uint64_t b)
@@ -379,7 +436,7 @@ int64_t Encoder::run(uint8_t **result)
     blk_.resize(nb_);
     wlev_.assign(n_ ? n_ : 1, -1);
     build_links();
-    if (o_.max_depth == 0) {
+    {
         // parallel parse; one resolver consumes the blocks in order as they finish
         std::vector<uint8_t> done(nb_, 0);
         std::mutex mu;
@@ -390,8 +447,14 @@ int64_t Encoder::run(uint8_t **result)
                     std::unique_lock<std::mutex> lk(mu);
                     cv.wait(lk, [&] { return done[b] != 0; });
                 }
-                resolve(b);
+                if (o_.max_depth)
+                    resolve_limited(b);
+                else
+                    resolve(b);
                 if (o_.flatten) { flatten(b); relevel(b); }
+                if (o_.verbose && (b + 1) % 64 == 0)
+                    fprintf(stderr, "aceapex_encode: %llu of %llu blocks resolved\n", (unsigned long long)(b + 1),
+                            (unsigned long long)nb_);
             }
         });
         parallel_for(nb_, threads, [&](uint64_t b) {
@@ -403,14 +466,6 @@ int64_t Encoder::run(uint8_t **result)
             cv.notify_all();
         });
         resolver.join();
-    } else {
-        for (uint64_t b = 0; b < nb_; b++) {
-            parse_limited(b);
-            if (o_.flatten) { flatten(b); relevel(b); }
-            if (o_.verbose && (b + 1) % 64 == 0)
-                fprintf(stderr, "aceapex_encode: depth-limited parse, %llu of %llu blocks\n",
-                        (unsigned long long)(b + 1), (unsigned long long)nb_);
-        }
     }
     std::vector<uint32_t>().swap(link_);
     std::vector<int32_t>().swap(wlev_);
