@@ -166,6 +166,24 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
 int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace,
                         size_t ws_bytes, void *hip_stream);
 
+/* Decode one stream exactly as aceapex_decode does, with no workspace
+ * argument and no allocation of any kind: for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The workspace is a library-static device array of
+ * ACEAPEX_NOALLOC_WORKSPACE_MAX bytes that every device the library runs on
+ * holds until the process ends; a stream whose aceapex_workspace_bytes
+ * exceeds it is refused with ACEAPEX_E_WORKSPACE before anything is
+ * enqueued.  The array belongs to the device that is current at the call,
+ * which must be the device of hip_stream.  Every call on one device shares
+ * that device's array and overwrites what the previous call left there, so
+ * calls that overlap on one device (other streams, other host threads) race:
+ * the caller must order them.  d_status may be NULL (the status then stays in
+ * the array, unreadable).  Asynchronous on hip_stream; returns the synchronous
+ * errors of aceapex_decode. */
+#define ACEAPEX_NOALLOC_WORKSPACE_MAX ((size_t)64 << 20)
+int aceapex_decode_noalloc(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, int32_t *d_status,
+                           void *hip_stream);
+
 /* Static English text for an error code (ACEAPEX_E_* above; "unknown error"
  * for any other value).  Pure host code. */
 const char *aceapex_strerror(int code);

@@ -66,6 +66,7 @@ class AceapexError(RuntimeError):
 
 
 EXPORTS = ("aceapex_probe", "aceapex_level_table", "aceapex_workspace_bytes", "aceapex_decode", "aceapex_decode_many",
+           "aceapex_decode_noalloc",
            "aceapex_strerror", "aceapex_last_hip_error", "aceapex_enc_defaults", "aceapex_encode",
            "aceapex_free", "aceapex_timing", "aceapex_timing_read", "aceapex_tuning_defaults",
            "aceapex_plan_create", "aceapex_plan_launch", "aceapex_plan_launch_graph", "aceapex_plan_set_tuning",
@@ -97,6 +98,8 @@ def load():
     lib.aceapex_workspace_bytes.restype = ctypes.c_size_t
     lib.aceapex_decode.argtypes = [ctypes.POINTER(Stream), vp, ctypes.c_uint64, vp, ctypes.c_size_t, vp, vp]
     lib.aceapex_decode.restype = ctypes.c_int
+    lib.aceapex_decode_noalloc.argtypes = [ctypes.POINTER(Stream), vp, ctypes.c_uint64, vp, vp]
+    lib.aceapex_decode_noalloc.restype = ctypes.c_int
     lib.aceapex_decode_many.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint32, vp, ctypes.c_size_t, vp]
     lib.aceapex_decode_many.restype = ctypes.c_int
     lib.aceapex_strerror.argtypes = [ctypes.c_int]
@@ -172,6 +175,13 @@ def decode(stream: Stream, d_out: int, out_capacity: int, d_ws: int, ws_bytes: i
            d_status: int, hip_stream: int) -> int:
     return load().aceapex_decode(ctypes.byref(stream), d_out, out_capacity, d_ws, ws_bytes,
                                  d_status, hip_stream)
+
+
+def decode_noalloc(stream: Stream, d_out: int, out_capacity: int, d_status: int, hip_stream: int) -> int:
+    return load().aceapex_decode_noalloc(ctypes.byref(stream), d_out, out_capacity, d_status, hip_stream)
+
+
+NOALLOC_WORKSPACE_MAX = 64 << 20  # ACEAPEX_NOALLOC_WORKSPACE_MAX
 
 
 def decode_many(descs, d_ws: int, ws_bytes: int, hip_stream: int) -> int:

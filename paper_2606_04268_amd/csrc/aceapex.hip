@@ -46,6 +46,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -1590,6 +1591,40 @@ int enqueue_plan(const PlanImpl *p, const Tune &tn, hipStream_t st, bool timed)
 
 }  // namespace
 
+// Workspace of aceapex_decode_noalloc: one library-static device array that
+// every device the library runs on holds until the process ends.  In host
+// code the symbol is only a stand-in; the array is reached through the
+// address hipGetSymbolAddress returns on each device (scratch_on_device).
+static constexpr size_t SCRATCH_BYTES = ACEAPEX_NOALLOC_WORKSPACE_MAX;
+static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_at[SCRATCH_DEVICES];  // device address of scratch, per device, once known
+
+// The address of the scratch array on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_on_device(uint8_t **at)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return ACEAPEX_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void *p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return hip_fail(e);
+        if (!p) return ACEAPEX_E_HIP;
+        g_scratch_at[dev] = (uint8_t *)p;
+    }
+    *at = g_scratch_at[dev];
+    return ACEAPEX_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info)
@@ -1648,6 +1683,22 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
     const size_t need = ws_single(stream->info).total;
     if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need) return ACEAPEX_E_WORKSPACE;
     return launch_single(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream);
+}
+
+int aceapex_decode_noalloc(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, int32_t *d_status,
+                           void *hip_stream)
+{
+    int rc = check_stream_args(stream, d_out, out_capacity);
+    if (rc) return rc;
+    if (ws_single(stream->info).total > SCRATCH_BYTES) return ACEAPEX_E_WORKSPACE;
+    uint8_t *ws = nullptr;
+    if ((rc = scratch_on_device(&ws))) return rc;
+    Batch B;
+    single_batch(*stream, d_out, ws, d_status, B);
+    // the same kernels as aceapex_decode, untimed (timing would create events)
+    enqueue_single(B, stream->h_levels, Tune(), (hipStream_t)hip_stream, false);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ACEAPEX_OK : hip_fail(e);
 }
 
 int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace, size_t ws_bytes,
