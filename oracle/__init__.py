@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
 class Opts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "block_log2", "min_match", "flatten", "max_depth", "chain_depth", "hash_bits",
-        "tiebreak", "chunk_log2")]
+        "tiebreak", "chunk_log2", "levels")]
 
 
 class Report(ctypes.Structure):
@@ -97,7 +97,7 @@ def _p(a: np.ndarray):
 
 
 DEFAULTS = dict(block_log2=20, min_match=4, flatten=0, max_depth=0, chain_depth=32,
-                hash_bits=22, tiebreak=0, chunk_log2=10)
+                hash_bits=22, tiebreak=0, chunk_log2=10, levels=1)
 
 
 def header_fields(stream) -> dict:

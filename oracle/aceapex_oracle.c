@@ -58,6 +58,7 @@ typedef struct {
     int32_t hash_bits;   /* log2 of the hash head table */
     int32_t tiebreak;    /* 0: equal length -> lowest level, 1: most recent */
     int32_t chunk_log2;  /* sequences per chunk-index entry */
+    int32_t levels;      /* 1: write lvl[] and the level table; 0: the four streams of Sec. 3.2 only */
 } orc_opts;
 
 typedef struct {
@@ -323,6 +324,10 @@ static void relevel_block(enc_t *e, uint64_t bs, uint64_t be, mvec_t *ms)
  *     off[n_seq] u32 absolute sources | cmd[] LEB128 literal runs (n_seq+1)
  *     | len[] LEB128 (length - min_match) | lvl[] LEB128 levels | lit[n_lit]
  *     every section padded with zeros to a multiple of 16 bytes
+ *   without levels (levels = 0: the four streams of Sec. 3.2 only) the level
+ *   flag is clear, the header's max_level and n_deep are 0, there is no level
+ *   table and every block's lvl[] is empty; a decoder then computes each
+ *   match's level from the definition of Sec. 7.1 as it goes
  */
 typedef struct {
     buf_t s;          /* block payloads, offsets relative to the first block */
@@ -372,11 +377,13 @@ static int write_block(writer_t *w, const enc_t *e, uint64_t bs, uint64_t be, co
             const match_t *m = &ms->m[i];
             buf_varint(&len, m->len - m0);
             buf_put(&off, &m->src, 4);
-            buf_varint(&lvl, (uint32_t)m->lvl);
-            if ((uint32_t)m->lvl > blk_max) blk_max = (uint32_t)m->lvl;
-            if ((uint32_t)m->lvl > w->max_level) w->max_level = (uint32_t)m->lvl;
-            if (m->lvl > 0) w->n_deep++;
-            count_level(w, (uint32_t)m->lvl);
+            if (e->o.levels) {
+                buf_varint(&lvl, (uint32_t)m->lvl);
+                if ((uint32_t)m->lvl > blk_max) blk_max = (uint32_t)m->lvl;
+                if ((uint32_t)m->lvl > w->max_level) w->max_level = (uint32_t)m->lvl;
+                if (m->lvl > 0) w->n_deep++;
+                count_level(w, (uint32_t)m->lvl);
+            }
             x += m->len;
         }
     }
@@ -409,7 +416,7 @@ static int opts_ok(const orc_opts *o)
     return o->block_log2 >= 3 && o->block_log2 <= 30 && o->min_match >= 4 && o->min_match <= 255 &&
            o->flatten >= 0 && o->flatten <= 2 && o->max_depth >= 0 && o->chain_depth >= 1 &&
            o->hash_bits >= 8 && o->hash_bits <= 28 && (o->tiebreak == 0 || o->tiebreak == 1) &&
-           o->chunk_log2 >= 0 && o->chunk_log2 <= 20;
+           o->chunk_log2 >= 0 && o->chunk_log2 <= 20 && (o->levels == 0 || o->levels == 1);
 }
 
 /* encode x[0..n) into a newly allocated stream; returns its length or < 0 */
@@ -446,7 +453,7 @@ int64_t orc_encode(const uint8_t *x, uint64_t n, const orc_opts *o, uint8_t **ou
         free(ms.m);
     }
     if (w.s.oom || w.oom) { rc = ORC_E_NOMEM; goto done; }
-    const uint64_t hist_n = (uint64_t)w.max_level + 1;
+    const uint64_t hist_n = o->levels ? (uint64_t)w.max_level + 1 : 0; /* no level table without levels */
     const uint64_t prefix = HDR_BYTES + (nb + 1) * 16 + pad16(4 * hist_n);
     total = prefix + w.s.len;
     final = calloc(total, 1);
@@ -461,7 +468,7 @@ int64_t orc_encode(const uint8_t *x, uint64_t n, const orc_opts *o, uint8_t **ou
     uint8_t *h = final;
     memcpy(h, "ACX1", 4);
     wr16(h + 4, 1);
-    uint16_t flags = FLAG_LEVELS;
+    uint16_t flags = o->levels ? FLAG_LEVELS : 0;
     if (o->flatten == 1) flags |= FLAG_FLATTEN;
     if (o->flatten == 2) flags |= FLAG_FLATTEN_LITONLY;
     if (o->max_depth > 0) flags |= FLAG_DEPTH_LIMITED;
@@ -506,10 +513,11 @@ typedef struct {
     uint64_t out_start, out_end;
 } sblk_t;
 
-/* header + block table + level table */
+/* header + block table + level table (present only with levels) */
 static uint64_t prefix_bytes(const shdr_t *h)
 {
-    return HDR_BYTES + ((uint64_t)h->n_blocks + 1) * 16 + pad16(4 * ((uint64_t)h->max_level + 1));
+    const uint64_t table = (h->flags & FLAG_LEVELS) ? pad16(4 * ((uint64_t)h->max_level + 1)) : 0;
+    return HDR_BYTES + ((uint64_t)h->n_blocks + 1) * 16 + table;
 }
 
 static int read_header(const uint8_t *s, uint64_t slen, shdr_t *h)
@@ -527,9 +535,11 @@ static int read_header(const uint8_t *s, uint64_t slen, shdr_t *h)
     h->n_seq = rd32(s + 40);
     h->n_deep = rd32(s + 44);
     h->n_chunks = rd32(s + 48);
-    if (!(h->flags & FLAG_LEVELS) || (h->flags & ~0xFu) || h->block_log2 < 3 || h->block_log2 > 30 ||
+    if ((h->flags & ~0xFu) || h->block_log2 < 3 || h->block_log2 > 30 ||
         h->min_match < 1 || h->chunk_log2 > 20 || s[11] != 0 || h->n >= ((uint64_t)1 << 32))
         return ORC_E_FORMAT;
+    /* without levels (the four streams of Sec. 3.2) the level fields are unused and zero */
+    if (!(h->flags & FLAG_LEVELS) && (h->max_level || h->n_deep)) return ORC_E_FORMAT;
     uint64_t B = (uint64_t)1 << h->block_log2;
     if ((h->n + B - 1) / B != h->n_blocks) return ORC_E_FORMAT;
     if (h->comp != slen) return ORC_E_FORMAT;
@@ -567,6 +577,7 @@ static int read_block(const uint8_t *s, const shdr_t *h, uint32_t b, sblk_t *k)
     k->lvl = p + q; q += pad16(k->lvl_bytes);
     k->lit = p + q; q += pad16(k->n_lit);
     if (q != o1 - o0) return ORC_E_CORRUPT;
+    if (!(h->flags & FLAG_LEVELS) && (k->lvl_bytes || k->max_level)) return ORC_E_CORRUPT;
     uint64_t B = (uint64_t)1 << h->block_log2;
     k->out_start = (uint64_t)b * B;
     k->out_end = k->out_start + B < h->n ? k->out_start + B : h->n;
@@ -628,18 +639,27 @@ static int run_block(const shdr_t *h, const sblk_t *k, exec_t *x, uint32_t b)
         q += r;
         if (x->progress) atomic_store_explicit(&x->progress[b], p - k->out_start, memory_order_release);
         if (i == k->n_seq) break;
-        uint32_t lm, lv;
+        uint32_t lm, lv = 0;
         u = get_varint(k->len + li, k->len_bytes - li, &lm);
         if (!u) return ORC_E_CORRUPT;
         li += u;
-        u = get_varint(k->lvl + vi, k->lvl_bytes - vi, &lv);
-        if (!u) return ORC_E_CORRUPT;
-        vi += u;
+        const int levels = (h->flags & FLAG_LEVELS) != 0;
+        if (levels) {
+            u = get_varint(k->lvl + vi, k->lvl_bytes - vi, &lv);
+            if (!u) return ORC_E_CORRUPT;
+            vi += u;
+        }
         uint64_t m = (uint64_t)lm + h->min_match;
         uint64_t s = rd32(k->off + i * 4);
         if (m > k->out_end - p) return ORC_E_CORRUPT;
         if (s + m > p) return ORC_E_CORRUPT; /* source must lie entirely before the destination */
-        if (lv > h->max_level || lv > k->max_level) return ORC_E_CORRUPT;
+        if (levels && (lv > h->max_level || lv > k->max_level)) return ORC_E_CORRUPT;
+        if (!levels) {
+            /* no stored level: the definition of Sec. 7.1 from the writers of the source bytes */
+            int32_t mx = -1;
+            for (uint64_t j = 0; j < m; j++) if (x->writer_lvl[s + j] > mx) mx = x->writer_lvl[s + j];
+            lv = (uint32_t)(mx + 1);
+        }
         if (x->wait && x->wait(x->wait_ctx, s, s + m)) return ORC_E_CORRUPT;
         memcpy(x->out + p, x->out + s, m); /* s + m <= p: the ranges never overlap */
         if (x->writer_lvl) for (uint64_t j = 0; j < m; j++) x->writer_lvl[p + j] = (int32_t)lv;
@@ -652,7 +672,7 @@ static int run_block(const shdr_t *h, const sblk_t *k, exec_t *x, uint32_t b)
         }
         if (lv > x->max_level) x->max_level = lv;
         if (lv > 0) x->n_deep++;
-        if (x->level_count) x->level_count[lv]++;
+        if (x->level_count && levels) x->level_count[lv]++;
         p += m;
         if (x->progress) atomic_store_explicit(&x->progress[b], p - k->out_start, memory_order_release);
     }
@@ -670,8 +690,15 @@ static int decode_all(const uint8_t *s, uint64_t slen, exec_t *x, uint64_t cap, 
     if (n_out) *n_out = h.n;
     if (cap < h.n) return ORC_E_CAPACITY;
     uint64_t seqs = 0;
+    const int levels = (h.flags & FLAG_LEVELS) != 0;
+    int32_t *own_wl = NULL; /* without levels, the writer-level map computes them */
+    if (!levels && !x->writer_lvl) {
+        own_wl = malloc((h.n ? h.n : 1) * sizeof(int32_t));
+        if (!own_wl) return ORC_E_NOMEM;
+        x->writer_lvl = own_wl;
+    }
     uint64_t *cnt = calloc((uint64_t)h.max_level + 1, sizeof(uint64_t));
-    if (!cnt) return ORC_E_NOMEM;
+    if (!cnt) { free(own_wl); return ORC_E_NOMEM; }
     x->level_count = cnt;
     for (uint32_t b = 0; b < h.n_blocks && !rc; b++) {
         sblk_t k;
@@ -680,12 +707,17 @@ static int decode_all(const uint8_t *s, uint64_t slen, exec_t *x, uint64_t cap, 
         seqs += k.n_seq;
     }
     x->level_count = NULL;
-    if (!rc && (seqs != h.n_seq || x->n_deep != h.n_deep || x->max_level != h.max_level)) rc = ORC_E_CORRUPT;
+    if (own_wl) {
+        free(own_wl);
+        x->writer_lvl = NULL;
+    }
+    if (!rc && seqs != h.n_seq) rc = ORC_E_CORRUPT;
+    if (!rc && levels && (x->n_deep != h.n_deep || x->max_level != h.max_level)) rc = ORC_E_CORRUPT;
     /* the level table must count exactly the matches of every level */
     const uint8_t *lt = s + HDR_BYTES + ((uint64_t)h.n_blocks + 1) * 16;
-    for (uint64_t l = 0; !rc && l <= h.max_level; l++)
+    for (uint64_t l = 0; levels && !rc && l <= h.max_level; l++)
         if (rd32(lt + 4 * l) != cnt[l]) rc = ORC_E_CORRUPT;
-    for (uint64_t q = 4 * ((uint64_t)h.max_level + 1); !rc && q < pad16(4 * ((uint64_t)h.max_level + 1)); q++)
+    for (uint64_t q = 4 * ((uint64_t)h.max_level + 1); levels && !rc && q < pad16(4 * ((uint64_t)h.max_level + 1)); q++)
         if (lt[q]) rc = ORC_E_CORRUPT;
     free(cnt);
     return rc;
@@ -725,6 +757,7 @@ typedef struct {
     const uint8_t *s;
     shdr_t h;
     uint8_t *out;
+    int32_t *writer_lvl; /* without stored levels: the writer level of every byte */
     _Atomic uint64_t *progress;
     _Atomic int failed;
     int nthreads;
@@ -752,6 +785,7 @@ static void *mt_worker(void *arg)
     exec_t x;
     memset(&x, 0, sizeof x);
     x.out = m->out;
+    x.writer_lvl = m->writer_lvl;
     x.progress = m->progress;
     x.wait = mt_wait;
     x.wait_ctx = m;
@@ -787,9 +821,13 @@ int orc_decode_mt(const uint8_t *s, uint64_t slen, uint8_t *out, uint64_t cap, i
     m.out = out;
     m.nthreads = nthreads;
     m.progress = calloc(m.h.n_blocks ? m.h.n_blocks : 1, sizeof(uint64_t));
+    if (!(m.h.flags & FLAG_LEVELS)) m.writer_lvl = malloc((m.h.n ? m.h.n : 1) * sizeof(int32_t));
     pthread_t *th = malloc(sizeof(pthread_t) * (size_t)nthreads);
     mt_arg_t *args = calloc((size_t)nthreads, sizeof(mt_arg_t));
-    if (!m.progress || !th || !args) { free(m.progress); free(th); free(args); return ORC_E_NOMEM; }
+    if (!m.progress || !th || !args || (!(m.h.flags & FLAG_LEVELS) && !m.writer_lvl)) {
+        free(m.progress); free(m.writer_lvl); free(th); free(args);
+        return ORC_E_NOMEM;
+    }
     int started = 0;
     for (int t = 0; t < nthreads; t++) {
         args[t].m = &m;
@@ -800,7 +838,7 @@ int orc_decode_mt(const uint8_t *s, uint64_t slen, uint8_t *out, uint64_t cap, i
     for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
     rc = started == nthreads ? ORC_OK : ORC_E_NOMEM;
     for (int t = 0; t < nthreads; t++) if (args[t].rc && rc == ORC_OK) rc = args[t].rc;
-    free(m.progress); free(th); free(args);
+    free(m.progress); free(m.writer_lvl); free(th); free(args);
     return rc;
 }
 
@@ -856,7 +894,7 @@ int orc_check(const uint8_t *x, uint64_t n, const uint8_t *s, uint64_t slen, orc
             rep->match_bytes += t->len;
         }
         rep->n_lit_bytes = n - rep->match_bytes;
-        if (rep->n_deep != h.n_deep) rc = ORC_E_CORRUPT;
+        if ((h.flags & FLAG_LEVELS) && rep->n_deep != h.n_deep) rc = ORC_E_CORRUPT;
     }
     free(out); free(wl); free(tok);
     return rc;

@@ -87,11 +87,15 @@ def random_tokens(rng: np.random.Generator, n: int, block_log2: int, min_match: 
 
 def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
           chunk_log2: int = 10, levels=None, flags: int = 8, max_depth: int = 0,
-          max_level=None, n_deep=None, level_counts=None, varint_width=None) -> np.ndarray:
+          max_level=None, n_deep=None, level_counts=None, varint_width=None,
+          with_levels: bool = True) -> np.ndarray:
     """Serialize token lists into the stream layout (levels from the definition by default).
 
     varint_width: None for minimal LEB128; an int w to pad every value to at
     least w bytes; a numpy Generator to draw each value's width from 1..4.
+    with_levels=False writes the four streams of Sec. 3.2 only: no lvl[]
+    sections, no level table, the levels flag clear and the header's level
+    fields zero.
     """
     def vw():
         if varint_width is None:
@@ -125,9 +129,10 @@ def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
             p += r
             ln += _varint(m - min_match, vw())
             off += int(s).to_bytes(4, "little")
-            lv += _varint(levels[mi], vw())
-            bmax = max(bmax, levels[mi])
-            deep += levels[mi] > 0
+            if with_levels:
+                lv += _varint(levels[mi], vw())
+                bmax = max(bmax, levels[mi])
+                deep += levels[mi] > 0
             mi += 1
             p += m
         if not seqs:
@@ -153,7 +158,10 @@ def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
             hist[lv] += 1
     if level_counts is not None:
         hist = list(level_counts)
-    hist_bytes = _pad(b"".join(int(v).to_bytes(4, "little") for v in hist))
+    hist_bytes = _pad(b"".join(int(v).to_bytes(4, "little") for v in hist)) if with_levels else b""
+    if not with_levels:
+        flags &= ~8
+        gmax = 0
     pos = 64 + table_len + len(hist_bytes)
     offsets = []
     for pl in payloads:
@@ -173,7 +181,7 @@ def build(blocks, lits: bytes, n: int, *, block_log2: int, min_match: int = 4,
     hdr[16:24] = n.to_bytes(8, "little")
     hdr[24:32] = comp.to_bytes(8, "little")
     hdr[32:36] = nb.to_bytes(4, "little")
-    hdr[36:40] = (gmax if max_level is None else max_level).to_bytes(4, "little")
+    hdr[36:40] = (gmax if max_level is None or not with_levels else max_level).to_bytes(4, "little")
     hdr[40:44] = tot_seq.to_bytes(4, "little")
     hdr[44:48] = (deep if n_deep is None else n_deep).to_bytes(4, "little")
     hdr[48:52] = tot_chunks.to_bytes(4, "little")

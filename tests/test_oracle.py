@@ -236,6 +236,8 @@ OPTION_GRID = [
     dict(block_log2=3, max_depth=2, chunk_log2=1),
     dict(block_log2=3, flatten=2, tiebreak=1, chunk_log2=0),
     dict(block_log2=3, flatten=1, tiebreak=1, chunk_log2=1),
+    dict(levels=0),
+    dict(block_log2=3, levels=0, chunk_log2=1),
 ]
 
 
@@ -417,3 +419,53 @@ def test_generated_workloads(kind, opts):
         assert rep.depth_violations == 0 and rep.max_level <= 7
     assert (oracle.decode_mt(s, 4) == x).all()
     assert oracle.header_fields(s)["content_hash"] == oracle.content_hash(x)
+
+
+# -------------------------------------------- streams without levels (Sec. 3.2)
+
+@pytest.mark.parametrize("kind", ["markov", "fastq", "wiki", "random"])
+@pytest.mark.parametrize("opts", [dict(), dict(flatten=1), dict(max_depth=4), dict(block_log2=12, chunk_log2=4)],
+                         ids=["plain", "flat", "d4", "small"])
+def test_four_stream_format(kind, opts):
+    """The paper's four streams (lit, len, off, cmd) with no lvl[] and no level
+    table decode to the same bytes, and the oracle assigns every match the
+    level of the definition (Sec. 7.1) from the writers of its source bytes:
+    equal to the levels the encoder computed while parsing and stored in the
+    levelled stream of the same input."""
+    x = synth.make(kind, 1 << 20, 0xACE0 + len(kind))
+    o = dict(dict(block_log2=16), **opts)
+    with_lv = oracle.encode(x, **o)
+    free = oracle.encode(x, levels=0, **o)
+    h = oracle.header_fields(free)
+    assert h["flags"] & 8 == 0 and h["max_level"] == 0 and h["n_deep"] == 0
+    assert free.size < with_lv.size
+    assert np.array_equal(oracle.decode(free), x)
+    assert np.array_equal(oracle.decode_mt(free, 3), x)
+    assert oracle.refdec(free) == x.tobytes()
+    a, b = oracle.tokens(with_lv), oracle.tokens(free)
+    assert np.array_equal(a, b)
+    rep = oracle.check(x, free)
+    assert rep.level_mismatch == 0 and rep.max_level == oracle.header_fields(with_lv)["max_level"]
+
+
+def test_four_stream_format_from_tokens():
+    """Hand-built token lists without levels: the oracle's levels equal the
+    ones computed in Python from the definition."""
+    rng = np.random.default_rng(21)
+    for bl in (4, 8, 12):
+        n = 3000
+        blocks, lits = streamgen.random_tokens(rng, n, bl, max_len=50)
+        s, want = streamgen.build(blocks, lits, n, block_log2=bl, chunk_log2=3, with_levels=False)
+        assert oracle.decode(s).tobytes() == want
+        t = toks(s)
+        py_lv, _ = py_levels_and_literals(t, n)
+        assert [lv for *_, lv in t] == py_lv
+
+
+def test_four_stream_format_rejects_level_fields():
+    x = synth.markov(50_000, 1)
+    s = oracle.encode(x, levels=0, block_log2=12)
+    bad = s.copy()
+    bad[36] = 1  # a max_level without levels
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(bad)
