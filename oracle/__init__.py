@@ -35,9 +35,9 @@ def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (plain C11, host only)."""
     import subprocess
 
-    src = os.path.join(_HERE, "aceapex_oracle.c")
+    srcs = [os.path.join(_HERE, "aceapex_oracle.c"), os.path.join(_HERE, "tans_oracle.c")]
     tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o", tmp, src, "-lpthread"]
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -82,6 +82,12 @@ def _load():
         lib.orc_check.restype = ctypes.c_int
         lib.orc_tokens.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64]
         lib.orc_tokens.restype = ctypes.c_int64
+        lib.orc_tans_counts.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint16)]
+        lib.orc_tans_counts.restype = ctypes.c_int
+        lib.orc_tans_encode.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_u8p)]
+        lib.orc_tans_encode.restype = ctypes.c_int64
+        lib.orc_tans_decode.argtypes = [_u8p, ctypes.c_uint64, _u8p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+        lib.orc_tans_decode.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -210,3 +216,39 @@ def tokens(stream) -> np.ndarray:
 
 
 from .refdec import refdec  # noqa: E402  (pure-Python second decoder)
+
+
+# ------------------------------------------------------------ tANS (literals)
+
+def tans_counts(x, table_log: int = 11) -> np.ndarray:
+    """Normalized counts (256 x u16, summing to 2^table_log) of the bytes x."""
+    xa = _buf(x)
+    c = (ctypes.c_uint16 * 256)()
+    rc = _load().orc_tans_counts(_p(xa), xa.size, table_log, c)
+    if rc:
+        raise OracleError(rc, "tans_counts")
+    return np.array(c[:], dtype=np.uint16)
+
+
+def tans_encode(x, table_log: int = 11, lanes: int = 1024) -> np.ndarray:
+    """tANS-code the bytes x into an ACT1 container (tans_oracle.c)."""
+    xa = _buf(x)
+    out = _u8p()
+    n = _load().orc_tans_encode(_p(xa), xa.size, table_log, lanes, ctypes.byref(out))
+    if n < 0:
+        raise OracleError(int(n), "tans_encode")
+    s = np.ctypeslib.as_array(out, shape=(n,)).copy()
+    _load().orc_free(out)
+    return s
+
+
+def tans_decode(container) -> np.ndarray:
+    """Decode an ACT1 container."""
+    c = _buf(container)
+    n = int(c[4:8].view(np.uint32)[0]) if c.size >= 8 else 0
+    out = np.empty(max(n, 1), dtype=np.uint8)
+    got = ctypes.c_uint64(0)
+    rc = _load().orc_tans_decode(_p(c), c.size, _p(out), out.size, ctypes.byref(got))
+    if rc:
+        raise OracleError(rc, "tans_decode")
+    return out[:got.value]
