@@ -41,7 +41,10 @@
  *     to a multiple of 16 bytes.  Every LEB128 value is at most 4 bytes long.
  *   flags: bit0 flattened within blocks (Sec. 3.3), bit1 flattened along
  *     literal-rooted chains only, bit2 depth-limited (Sec. 7.4), bit3 levels
- *     present (always set).
+ *     present.  Without bit3 the stream holds the four streams of Sec. 3.2
+ *     only: max_level and n_deep are 0, there is no level table (the first
+ *     block follows the block table) and every block's lvl[] is empty; the
+ *     decoder then derives the levels on the device (aceapex_decode_derive).
  *
  * Conventions.  All pointers named d_* are device pointers on the current HIP
  * device; h_* are host pointers.  The caller owns every buffer.  Calls that
@@ -135,9 +138,10 @@ int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info)
 int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *counts, uint32_t n);
 
 /* Device workspace, in bytes, that aceapex_decode_many needs for these n
- * descriptors (n = 1 for aceapex_decode): per chunk a 48-byte descriptor of
+ * descriptors (n = 1 for aceapex_decode): per chunk a 64-byte descriptor of
  * its slices of the Sec. 3.2 streams, per level of Sec. 7.1 three slot
- * counters, and 12 bytes per match for the level-grouped match records.  Pure
+ * counters, and 12 bytes per match for the level-grouped match records; for
+ * a stream without levels, the workspace of aceapex_decode_derive.  Pure
  * host code; returns 0 when a descriptor's info is inconsistent. */
 size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n);
 
@@ -151,6 +155,29 @@ size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n);
 int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capacity,
                    void *d_workspace, size_t ws_bytes, int32_t *d_status, void *hip_stream);
 
+/* Decode one stream, deriving every match's level on the device instead of
+ * reading lvl[] (Sec. 7.1: a match's level is 0 when every source byte is a
+ * literal, else 1 + the highest level among the matches that wrote its source
+ * bytes; the paper computes them on the CPU, Sec. 4.4).  aceapex_decode takes
+ * this path for a stream without levels (flag bit3 clear); this call takes it
+ * for any stream, ignoring lvl[] and the level table.  The matches run level
+ * by level as their levels are found: at level k each waiting match resumes a
+ * scan of the writers of its source bytes, parks on the first writer that has
+ * not run, or runs when every writer has.  d_levels, when not NULL, receives
+ * each match's level in stream order (n_seq u32, 4-byte aligned).  The
+ * workspace must hold aceapex_workspace_bytes_derive(&stream->info) bytes,
+ * 256-byte aligned.  The number of levels is found on the device: the call
+ * reads a queue length back from the device every few levels (synchronising
+ * hip_stream) and returns once the last level is enqueued.  Errors as
+ * aceapex_decode; a stream whose sources admit no order fails with
+ * ACEAPEX_E_CORRUPT in *d_status. */
+int aceapex_decode_derive(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, void *d_workspace,
+                          size_t ws_bytes, uint32_t *d_levels, int32_t *d_status, void *hip_stream);
+
+/* Workspace of aceapex_decode_derive for a stream with this header (0 when
+ * the header is inconsistent).  Pure host code. */
+size_t aceapex_workspace_bytes_derive(const aceapex_info *info);
+
 /* Decode n independent streams (Sec. 7.5: blocks and streams are independent)
  * as one batch on hip_stream.  h_descs is a host array; the workspace must
  * hold aceapex_workspace_bytes(h_descs, n).  When every descriptor carries
@@ -160,7 +187,9 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
  * overflow the 32-bit indexes of one sequence, runs as several consecutive
  * sequences.  Without the tables the streams are decoded one after the other.
  * Returns the first synchronous error; per-stream device errors go to each
- * d_status.  Host level tables are checked as in aceapex_decode: a table
+ * d_status.  A stream without levels is refused (ACEAPEX_E_UNSUPPORTED): its
+ * derivation reads back from the device, one stream per call.  Host level
+ * tables are checked as in aceapex_decode: a table
  * whose counts do not add up to n_seq is refused (ACEAPEX_E_FORMAT), one that
  * differs from the stream's own table fails that stream (ACEAPEX_E_CORRUPT). */
 int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspace,
@@ -183,6 +212,21 @@ int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspa
 #define ACEAPEX_NOALLOC_WORKSPACE_MAX ((size_t)64 << 20)
 int aceapex_decode_noalloc(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, int32_t *d_status,
                            void *hip_stream);
+
+/* Decode one stream on the host CPU into h_out, for requests a GPU launch
+ * serves slower: small streams, and very deep ones whose wavefront pays one
+ * level boundary per level (Sec. 7.2 finds such a stream slower on the GPU;
+ * Sec. 8.2 suggests choosing the device per input).  Blocks are decoded in
+ * parallel by `threads` host threads (0 = all), each block's sequences in
+ * order (Sec. 3.2), a copy from an earlier block waiting until that block has
+ * published its source bytes (Sec. 3.1: blocks carry no context, sources are
+ * absolute).  h_stream is the whole stream (len = comp_bytes); h_out holds at
+ * least decoded_bytes.  Synchronous; the lvl[] section and the level table
+ * are not used.  Returns ACEAPEX_OK, ACEAPEX_E_INVAL, ACEAPEX_E_FORMAT,
+ * ACEAPEX_E_CAPACITY, ACEAPEX_E_UNSUPPORTED, ACEAPEX_E_NOMEM or
+ * ACEAPEX_E_CORRUPT (h_out then holds unspecified bytes; no write leaves
+ * [h_out, h_out + decoded_bytes)). */
+int aceapex_decode_host(const void *h_stream, size_t len, void *h_out, uint64_t out_capacity, uint32_t threads);
 
 /* Static English text for an error code (ACEAPEX_E_* above; "unknown error"
  * for any other value).  Pure host code. */
@@ -292,6 +336,8 @@ typedef struct {
     uint32_t threads;     /* host threads, 0 = all                                                */
     uint32_t verbose;     /* nonzero: the in-order pass reports its progress on stderr every 64  */
                           /* blocks                                                               */
+    uint32_t levels;      /* 1: store lvl[] and the level table (1); 0: the four streams of       */
+                          /* Sec. 3.2 only, levels derived by the decoder                          */
 } aceapex_enc_opts;
 
 /* Fill *o with the defaults above.  Pure host code. */

@@ -14,7 +14,8 @@ from . import _abi
 from ._abi import AceapexError, Info
 
 __all__ = ["AceapexError", "Info", "DeviceStream", "probe", "encode", "to_device",
-           "workspace_bytes", "decode", "decode_many", "check_status", "content_hash", "Plan"]
+           "workspace_bytes", "decode", "decode_derive", "decode_host", "decode_many", "check_status",
+           "content_hash", "Plan"]
 
 
 def _torch():
@@ -36,7 +37,8 @@ def encode(data, *, with_hash: bool = True, **opts) -> np.ndarray:
     """Encode host bytes into a stream (host encoder in libaceapex.so).
 
     Options (see aceapex_enc_opts): block_log2, min_match, flatten, max_depth,
-    chain_depth, hash_bits, tiebreak, chunk_log2, threads, verbose.
+    chain_depth, hash_bits, tiebreak, chunk_log2, threads, verbose, levels
+    (0: the four streams of Sec. 3.2 only; the decoder derives the levels).
     """
     o = _abi.enc_defaults()
     for k, v in opts.items():
@@ -151,6 +153,47 @@ def decode_many(streams, outs=None, workspace=None, statuses=None, stream=None):
     if rc:
         raise AceapexError(rc, "decode_many")
     return outs, statuses
+
+
+def decode_derive(ds: DeviceStream, out=None, workspace=None, status=None, levels: bool = True, stream=None):
+    """Enqueue a decode of ``ds`` that derives every match's level on the
+    device (aceapex_decode_derive); returns (out, status, levels) where levels
+    is a uint32-valued int32 tensor of each match's level in stream order (or
+    None).  The call reads a queue length back from the device every few
+    levels, so it returns once the last level is enqueued."""
+    torch = _torch()
+    dev = ds.comp.device
+    mine = []
+    if out is None:
+        out = torch.empty(max(ds.n, 1), dtype=torch.uint8, device=dev)
+        mine.append(out)
+    need = _abi.workspace_bytes_derive(ds.info)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        mine.append(workspace)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+        mine.append(status)
+    lv = torch.empty(max(int(ds.info.n_seq), 1), dtype=torch.int32, device=dev) if levels else None
+    if lv is not None:
+        mine.append(lv)
+    _used_on(stream, mine)
+    rc = _abi.decode_derive(ds.abi(), out.data_ptr(), out.numel(), workspace.data_ptr(), workspace.numel(),
+                            lv.data_ptr() if lv is not None else None, status.data_ptr(), _stream_handle(stream))
+    if rc:
+        raise AceapexError(rc, "decode_derive")
+    return out, status, lv
+
+
+def decode_host(stream, threads: int = 0) -> np.ndarray:
+    """Decode a host stream on the host CPU (aceapex_decode_host)."""
+    s = np.ascontiguousarray(np.frombuffer(bytes(stream), np.uint8) if not isinstance(stream, np.ndarray)
+                             else stream, dtype=np.uint8)
+    out = np.empty(int(probe(s).decoded_bytes), dtype=np.uint8)
+    rc = _abi.decode_host(s, out, threads)
+    if rc:
+        raise AceapexError(rc, "decode_host")
+    return out
 
 
 def check_status(status) -> None:

@@ -47,7 +47,7 @@ class EncOpts(ctypes.Structure):
     """aceapex_enc_opts."""
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "block_log2", "min_match", "flatten", "max_depth", "chain_depth", "hash_bits",
-        "tiebreak", "chunk_log2", "threads", "verbose")]
+        "tiebreak", "chunk_log2", "threads", "verbose", "levels")]
 
 
 class Tuning(ctypes.Structure):
@@ -66,7 +66,7 @@ class AceapexError(RuntimeError):
 
 
 EXPORTS = ("aceapex_probe", "aceapex_level_table", "aceapex_workspace_bytes", "aceapex_decode", "aceapex_decode_many",
-           "aceapex_decode_noalloc",
+           "aceapex_decode_noalloc", "aceapex_decode_host", "aceapex_decode_derive", "aceapex_workspace_bytes_derive",
            "aceapex_strerror", "aceapex_last_hip_error", "aceapex_enc_defaults", "aceapex_encode",
            "aceapex_free", "aceapex_timing", "aceapex_timing_read", "aceapex_tuning_defaults",
            "aceapex_plan_create", "aceapex_plan_launch", "aceapex_plan_launch_graph", "aceapex_plan_set_tuning",
@@ -100,6 +100,12 @@ def load():
     lib.aceapex_decode.restype = ctypes.c_int
     lib.aceapex_decode_noalloc.argtypes = [ctypes.POINTER(Stream), vp, ctypes.c_uint64, vp, vp]
     lib.aceapex_decode_noalloc.restype = ctypes.c_int
+    lib.aceapex_decode_derive.argtypes = [ctypes.POINTER(Stream), vp, ctypes.c_uint64, vp, ctypes.c_size_t, vp, vp, vp]
+    lib.aceapex_decode_derive.restype = ctypes.c_int
+    lib.aceapex_workspace_bytes_derive.argtypes = [ctypes.POINTER(Info)]
+    lib.aceapex_workspace_bytes_derive.restype = ctypes.c_size_t
+    lib.aceapex_decode_host.argtypes = [vp, ctypes.c_size_t, vp, ctypes.c_uint64, ctypes.c_uint32]
+    lib.aceapex_decode_host.restype = ctypes.c_int
     lib.aceapex_decode_many.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint32, vp, ctypes.c_size_t, vp]
     lib.aceapex_decode_many.restype = ctypes.c_int
     lib.aceapex_strerror.argtypes = [ctypes.c_int]
@@ -154,9 +160,12 @@ def probe(prefix) -> Info:
 
 
 def level_table(stream, info: Info):
-    """aceapex_level_table on a host stream: a ctypes uint32 array of max_level + 1 counts."""
+    """aceapex_level_table on a host stream: a ctypes uint32 array of max_level + 1
+    counts, or None for a stream without levels (the four streams of Sec. 3.2)."""
     import numpy as np
 
+    if not info.flags & 8:
+        return None
     buf = np.ascontiguousarray(stream, dtype=np.uint8)
     n = info.max_level + 1
     counts = (ctypes.c_uint32 * n)()
@@ -182,6 +191,22 @@ def decode_noalloc(stream: Stream, d_out: int, out_capacity: int, d_status: int,
 
 
 NOALLOC_WORKSPACE_MAX = 64 << 20  # ACEAPEX_NOALLOC_WORKSPACE_MAX
+
+
+def decode_derive(stream: Stream, d_out: int, out_capacity: int, d_ws: int, ws_bytes: int, d_levels,
+                  d_status: int, hip_stream: int) -> int:
+    return load().aceapex_decode_derive(ctypes.byref(stream), d_out, out_capacity, d_ws, ws_bytes, d_levels,
+                                        d_status, hip_stream)
+
+
+def workspace_bytes_derive(info: Info) -> int:
+    return int(load().aceapex_workspace_bytes_derive(ctypes.byref(info)))
+
+
+def decode_host(stream, out, threads: int = 0) -> int:
+    """aceapex_decode_host on host numpy buffers (stream: uint8, out: uint8 writable)."""
+    return load().aceapex_decode_host(stream.ctypes.data, stream.size, out.ctypes.data if out.size else None,
+                                      out.size, threads)
 
 
 def decode_many(descs, d_ws: int, ws_bytes: int, hip_stream: int) -> int:
@@ -272,3 +297,4 @@ def plan_tune(plan: int, hip_stream: int, reps: int) -> Tuning:
 
 def plan_destroy(plan: int) -> None:
     load().aceapex_plan_destroy(plan)
+

@@ -51,6 +51,7 @@
 #include <vector>
 
 #include "aceapex.h"
+#include "internal.h"
 
 namespace {
 
@@ -89,8 +90,10 @@ struct ChunkDesc {
     uint32_t lit_at, lit_n;
     uint32_t off_at;              // first off[] entry of the chunk
     uint32_t nseq_last;           // sequences in the chunk | (1 << 31) if it holds the trailing run
+    uint32_t seq0;                // index of the chunk's first match in its stream
+    uint32_t pad[3];
 };
-static_assert(sizeof(ChunkDesc) == 48, "descriptor layout");
+static_assert(sizeof(ChunkDesc) == 64, "descriptor layout");
 
 // One stream as the kernels see it.
 struct Job {
@@ -104,6 +107,8 @@ struct Job {
     uint32_t max_level, n_chunks, n_seq;
     uint32_t c0, b0;     // first global chunk and block of the stream in its batch
     uint32_t lv0;        // first entry of the stream in the per-(stream, level) arrays
+    uint32_t table;      // 1: the stream stores lvl[] and a level table; 0: the four streams of Sec. 3.2 only
+    uint32_t derive;     // 1: levels derived on the device (records in stream order, single stream only)
 };
 
 // A decode: one stream (jobs == nullptr) or a batch of streams.
@@ -122,7 +127,23 @@ struct Batch {
     uint32_t xcd_parts;         // k_level: contiguous parts of a level's records (1..8)
     uint32_t has_sig;           // single stream: the host scheduled the levels from a table
     uint64_t level_sig;         //   whose signature (level_signature) is this
+    // levels derived on the device (single stream): per match, in stream order
+    uint32_t *dlevel;           // level once run, NONE before
+    uint32_t *dhead, *dnext;    // matches parked on a match (linked list through dnext)
+    uint32_t *dcur, *dmax;      // where the scan of its source resumes, 1 + highest level seen
+    uint32_t *dq[2];            // matches to scan at the next level (two, by level parity)
+    uint32_t *dready;           // matches found ready at this level
+    uint32_t *dpage;            // per 256 output bytes: first match whose dst is at or past it
+    uint32_t *dcnt;             // counters (DC_*)
 };
+
+constexpr uint32_t NONE = 0xffffffffu;
+// counters of the derive path
+constexpr uint32_t DC_Q = 0;      // [2] matches queued to scan, by level parity
+constexpr uint32_t DC_READY = 2;  // [2] matches ready, by level parity
+constexpr uint32_t DC_DONE = 4;   // matches run
+constexpr uint32_t DC_LEVELS = 5; // levels run (highest level + 1)
+constexpr uint32_t DC_N = 8;
 
 // Signature of a level table: the sum over levels k of a 64-bit mix of
 // (k, count_k) (the SplitMix64 finalizer).  The single-stream decode sizes its
@@ -487,7 +508,12 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
     __shared__ uint64_t tmp[NT / 64];
     const uint32_t t = threadIdx.x;
 
-    if (!B.jobs && blockIdx.x == 0) {
+    if (!B.jobs && blockIdx.x == 0 && B.one.derive) {
+        // single stream without levels: the counters of the level derivation
+        if (t < DC_N) B.dcnt[t] = 0;
+        if (t == 0) *B.one.status = 0;
+    }
+    if (!B.jobs && blockIdx.x == 0 && !B.one.derive) {
         // single stream: its level table -> record slots of every level
         const Job &j = B.one;
         const uint64_t lvl_tab = HDR + 16ull * (j.n_blocks + 1);
@@ -534,7 +560,7 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
         const uint32_t b = gb - j.b0;
         const uint64_t Bsz = (uint64_t)1 << j.block_log2;
         const uint32_t K = 1u << j.chunk_log2;
-        const uint64_t prefix = HDR + 16ull * (j.n_blocks + 1) + pad16(4ull * (j.max_level + 1));
+        const uint64_t prefix = HDR + 16ull * (j.n_blocks + 1) + (j.table ? pad16(4ull * (j.max_level + 1)) : 0);
         const uint8_t *tb = j.comp + HDR + 16ull * b;
         const uint64_t o0 = ld64(tb), o1 = ld64(tb + 16);
         const uint32_t sb0 = ld32(tb + 8), cb0 = ld32(tb + 12), sb1 = ld32(tb + 24), cb1 = ld32(tb + 28);
@@ -587,6 +613,8 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
             cd.lit_at = (uint32_t)lit_at + q0; cd.lit_n = q1 - q0;
             cd.off_at = (uint32_t)(off_at + 4ull * c * K);
             cd.nseq_last = n_in | (last ? 0x80000000u : 0u);
+            cd.seq0 = sb0 + c * K;
+            cd.pad[0] = cd.pad[1] = cd.pad[2] = 0;
             if (!cok) {  // a descriptor that k_parse rejects
                 cd.out_len = 0xffffffffu;
                 all = false;
@@ -658,7 +686,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     }
     const uint32_t ns = d.nseq_last & 0x7fffffffu;
     const uint32_t ncmd = ns + (d.nseq_last >> 31);
-    const bool one_byte = d.cmd_n == ncmd && d.len_n == ns && d.lvl_n == ns;
+    const bool one_byte = d.cmd_n == ncmd && d.len_n == ns && d.lvl_n == (j.table ? ns : 0u);
     const uint32_t e0 = t * PER;
 
     // Literal placement.  When the chunk's output span fits the LDS tile, the
@@ -699,7 +727,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     if (one_byte) {
         const uint32_t cw = bytes4(j.comp + d.cmd_at, e0, ncmd);
         const uint32_t lw = bytes4(j.comp + d.len_at, e0, ns);
-        const uint32_t vw = bytes4(j.comp + d.lvl_at, e0, ns);
+        const uint32_t vw = j.table ? bytes4(j.comp + d.lvl_at, e0, ns) : 0u;
         if ((cw | lw | vw) & 0x80808080u) bad = true;  // a continuation byte where every value is one byte
         if (tail_cmd) {
             rt = j.comp[d.cmd_at + NT * PER];
@@ -714,7 +742,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     } else {
         bool ok = true;
         const uint32_t wv = __builtin_amdgcn_readfirstlane(wave);
-        if (wv < 3) {  // waves 0, 1, 2: the cmd, len and lvl slices
+        if (wv < (j.table ? 3u : 2u)) {  // waves 0, 1, 2: the cmd, len and lvl slices
             const uint32_t at = wv == 0 ? d.cmd_at : wv == 1 ? d.len_at : d.lvl_at;
             const uint32_t nb = wv == 0 ? d.cmd_n : wv == 1 ? d.len_n : d.lvl_n;
             uint32_t *vals = wv == 0 ? L.u.v.run : wv == 1 ? L.u.v.mlen : L.u.v.lvl;
@@ -732,7 +760,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
             const uint32_t e = e0 + u;
             r[u] = e < ncmd ? L.u.v.run[e] : 0;
             m[u] = e < ns ? L.u.v.mlen[e] + j.min_match : 0;
-            l[u] = e < ns ? L.u.v.lvl[e] : 0;
+            l[u] = e < ns && j.table ? L.u.v.lvl[e] : 0;
         }
         if (tail_cmd) rt = L.u.v.run[NT * PER];
     }
@@ -908,6 +936,28 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
         }
     }
 
+    if (!BATCH && j.derive) {
+        // levels derived on the device: every match -> its record in stream
+        // order, with the state of its derivation: not run, nothing parked
+        // on it, its source to scan
+        for (uint32_t u = 0; u < PER; u++) {
+            if (e0 + u >= ns) continue;
+            const uint32_t i = d.seq0 + e0 + u;
+            if ((uint64_t)src[u] + m[u] > dst[u] || i >= j.n_seq) {
+                bad = true;
+                continue;
+            }
+            uint32_t *rr = B.recs + 3ull * i;
+            rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u];
+            B.dlevel[i] = NONE;
+            B.dhead[i] = NONE;
+            B.dcur[i] = src[u];
+            B.dmax[i] = 0;
+        }
+        if (bad) fail(j, ACEAPEX_E_CORRUPT);
+        return;
+    }
+
     // every match -> record in the slots of its level
     const uint32_t tag = sj << LEN_BITS;
 #pragma unroll
@@ -1055,6 +1105,211 @@ __global__ void __launch_bounds__(NT_TAIL) k_tail(Batch B, uint32_t k0)
     }
 }
 
+// ------------------------------------------------------- level derivation
+
+// A stream without stored levels (the four streams of Sec. 3.2) is decoded
+// by deriving each match's level on the device while running the wavefront
+// (Sec. 7.1: a match's level is 0 when every source byte is a literal, else
+// 1 + the highest level among the matches that wrote its source bytes).
+// The parse leaves the matches in stream order, that is by destination.  At
+// level k, every queued match scans its source range writer by writer from
+// where its scan stopped: a literal run is skipped, a match that has run
+// adds its level, and the first match that has not run yet stops the scan --
+// the scanning match parks on that writer's list.  A match whose scan reaches
+// the end of its source is ready: every writer of its source has run, at
+// level k - 1 at the latest, and the writer that woke it at level k - 1, so
+// its level is k.  The ready matches then run (their copies read only bytes
+// final before level k) and wake the matches parked on them into the queue
+// of level k + 1.  Each match parks at most once per writer, so the work is
+// the matches plus the writer edges, at two launches per level; once the
+// queue is small a single workgroup runs the remaining levels with workgroup
+// barriers and stops by itself when the queue is empty.
+
+// A load that reads the value in L2, past this CU's L1: for words that other
+// waves change with atomics while a kernel runs.
+__device__ __forceinline__ uint32_t load_l2(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The match that writes output byte b (of N), or NONE when a literal does;
+// run_end gets the end of the run of bytes that writer (or literal run)
+// covers.  B.dpage[b >> 8] is the first match whose destination is at or
+// past the start of b's 256-byte page.
+__device__ __forceinline__ uint32_t writer_of(const Batch &B, uint32_t b, uint32_t M, uint32_t N, uint32_t &run_end)
+{
+    uint32_t c = B.dpage[b >> 8];
+    while (c < M && B.recs[3ull * c] <= b) c++;  // c: the first match whose destination is past b
+    if (c > 0) {
+        const uint32_t *r = B.recs + 3ull * (c - 1);
+        if ((uint64_t)b < (uint64_t)r[0] + r[2]) {
+            run_end = r[0] + r[2];
+            return c - 1;
+        }
+    }
+    run_end = c < M ? B.recs[3ull * c] : N;
+    return NONE;
+}
+
+// Resume the scan of match m's source; true when every writer has run.
+__device__ __forceinline__ bool derive_scan(const Batch &B, uint32_t m, uint32_t M, uint32_t N)
+{
+    const uint32_t *r = B.recs + 3ull * m;
+    const uint32_t end = r[1] + r[2];
+    uint32_t b = B.dcur[m], mx = B.dmax[m];
+    while (b < end) {
+        uint32_t run_end;
+        const uint32_t w = writer_of(B, b, M, N, run_end);
+        if (w != NONE) {
+            const uint32_t lv = B.dlevel[w];
+            if (lv == NONE) {  // not run yet: park on it
+                B.dcur[m] = b;
+                B.dmax[m] = mx;
+                B.dnext[m] = atomicExch(&B.dhead[w], m);
+                return false;
+            }
+            mx = max(mx, lv + 1);
+        }
+        b = min(end, max(run_end, b + 1));
+    }
+    return true;
+}
+
+// Append the lanes' items (flag set) to list[*count...] with one atomic per wave.
+__device__ __forceinline__ void wave_append(uint32_t *list, uint32_t *count, bool flag, uint32_t item)
+{
+    const uint64_t mask = __ballot(flag);
+    if (!mask) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t leader = (uint32_t)__builtin_ctzll(mask);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+    base = __shfl(base, (int)leader, 64);
+    if (flag) list[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] = item;
+}
+
+// Run the ready match m (NONE for an idle lane) at level k: its copy, its
+// level, and the matches parked on it into the queue of level k + 1.  Every
+// lane of the wave calls it.
+__device__ __forceinline__ void derive_run(const Batch &B, uint32_t m, uint32_t k)
+{
+    uint8_t *ob[1] = {B.one.out};
+    uint32_t on[1] = {B.one.n};
+    int32_t *sp[1] = {B.one.status};
+    uint32_t dst[1] = {0}, src[1] = {0}, len[1] = {0};
+    if (m != NONE) {
+        const uint32_t *r = B.recs + 3ull * m;
+        dst[0] = r[0];
+        src[0] = r[1];
+        len[0] = r[2];
+    }
+    run_records<1>(ob, on, sp, dst, src, len, B.long_copy);
+    uint32_t n_wake = 0;
+    if (m != NONE) {
+        B.dlevel[m] = k;
+        for (uint32_t x = load_l2(&B.dhead[m]); x != NONE && n_wake <= B.n_seq; x = B.dnext[x]) n_wake++;
+    }
+    // the wave's wake-ups: one atomic, then each lane writes its list
+    const uint64_t incl = wave_incl_scan64(n_wake);
+    const uint64_t total = (uint64_t)__shfl((unsigned long long)incl, 63, 64);
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(&B.dcnt[DC_Q + ((k + 1) & 1)], (uint32_t)total);
+    base = __shfl(base, 63, 64) + (uint32_t)(incl - n_wake);
+    uint32_t *q = B.dq[(k + 1) & 1];
+    if (m != NONE) {
+        uint32_t i = 0;
+        for (uint32_t x = load_l2(&B.dhead[m]); x != NONE && i < n_wake; x = B.dnext[x], i++) q[base + i] = x;
+    }
+    const uint64_t ran = __ballot(m != NONE);
+    if ((threadIdx.x & 63) == 0 && ran) atomicAdd(&B.dcnt[DC_DONE], (uint32_t)__popcll(ran));
+}
+
+// Per 256-byte page of the output: the first match whose destination is at
+// or past the page's start.
+__global__ void __launch_bounds__(NT) k_pages(Batch B)
+{
+    if (*B.one.status) return;
+    const uint32_t M = B.n_seq, np = (B.one.n >> 8) + 1;
+    for (uint32_t r = blockIdx.x * NT + threadIdx.x; r <= M; r += gridDim.x * NT) {
+        const uint32_t lo = r == 0 ? 0u : (B.recs[3ull * (r - 1)] >> 8) + 1;
+        const uint32_t hi = r == M ? np - 1 : B.recs[3ull * r] >> 8;
+        for (uint32_t pg = lo; pg <= hi && pg < np; pg++) B.dpage[pg] = r;
+    }
+}
+
+// Level k, scan: every queued match (at level 0, every match) resumes its scan.
+__global__ void __launch_bounds__(NT) k_derive_scan(Batch B, uint32_t k)
+{
+    if (*B.one.status) return;
+    const uint32_t M = B.n_seq, N = B.one.n;
+    const uint32_t cnt = k == 0 ? M : B.dcnt[DC_Q + (k & 1)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.dcnt[DC_Q + ((k + 1) & 1)] = 0;
+    const uint32_t *q = B.dq[k & 1];
+    for (uint32_t i0 = blockIdx.x * NT;; i0 += gridDim.x * NT) {
+        const uint32_t i = i0 + threadIdx.x;
+        if (__ballot(i < cnt) == 0) break;
+        const uint32_t m = i < cnt ? (k == 0 ? i : q[i]) : NONE;
+        const bool ready = m < M && derive_scan(B, m, M, N);
+        wave_append(B.dready, &B.dcnt[DC_READY + (k & 1)], ready, m);
+    }
+}
+
+// Level k, run: every ready match runs and wakes the matches parked on it.
+__global__ void __launch_bounds__(NT) k_derive_run(Batch B, uint32_t k)
+{
+    if (*B.one.status) return;
+    const uint32_t cnt = B.dcnt[DC_READY + (k & 1)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        B.dcnt[DC_READY + ((k + 1) & 1)] = 0;
+        if (cnt) atomicMax(&B.dcnt[DC_LEVELS], k + 1);
+    }
+    for (uint32_t i0 = blockIdx.x * NT;; i0 += gridDim.x * NT) {
+        const uint32_t i = i0 + threadIdx.x;
+        if (__ballot(i < cnt) == 0) break;
+        derive_run(B, i < cnt ? B.dready[i] : NONE, k);
+    }
+}
+
+// The remaining levels from k0 in one workgroup, until the queue is empty.
+__global__ void __launch_bounds__(NT_TAIL) k_derive_tail(Batch B, uint32_t k0)
+{
+    if (*B.one.status) return;
+    const uint32_t M = B.n_seq, N = B.one.n;
+    for (uint32_t k = k0; k < k0 + M + 1; k++) {
+        const uint32_t cnt = load_l2(&B.dcnt[DC_Q + (k & 1)]);
+        __syncthreads();
+        if (cnt == 0) break;
+        if (threadIdx.x == 0) {
+            B.dcnt[DC_Q + ((k + 1) & 1)] = 0;
+            B.dcnt[DC_READY + (k & 1)] = 0;
+        }
+        __syncthreads();
+        const uint32_t *q = B.dq[k & 1];
+        for (uint32_t i0 = 0;; i0 += NT_TAIL) {
+            const uint32_t i = i0 + threadIdx.x;
+            if (__ballot(i < cnt) == 0) break;
+            const uint32_t m = i < cnt ? q[i] : NONE;
+            const bool ready = m < M && derive_scan(B, m, M, N);
+            wave_append(B.dready, &B.dcnt[DC_READY + (k & 1)], ready, m);
+        }
+        __syncthreads();
+        const uint32_t nr = load_l2(&B.dcnt[DC_READY + (k & 1)]);
+        if (threadIdx.x == 0 && nr) atomicMax(&B.dcnt[DC_LEVELS], k + 1);
+        for (uint32_t i0 = 0;; i0 += NT_TAIL) {
+            const uint32_t i = i0 + threadIdx.x;
+            if (__ballot(i < nr) == 0) break;
+            derive_run(B, i < nr ? B.dready[i] : NONE, k);
+        }
+        __syncthreads();
+    }
+}
+
+// Every match must have run (a stream whose sources form no valid order fails).
+__global__ void k_derive_final(Batch B)
+{
+    if (threadIdx.x == 0 && *B.one.status == 0 && B.dcnt[DC_DONE] != B.n_seq) fail(B.one, ACEAPEX_E_CORRUPT);
+}
+
 // ----------------------------------------------------------------- host side
 
 thread_local int g_last_hip = 0;
@@ -1110,9 +1365,12 @@ inline uint16_t rd16h(const uint8_t *p) { uint16_t v; memcpy(&v, p, 2); return v
 inline uint32_t rd32h(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
 inline uint64_t rd64h(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
 
+bool has_table(const aceapex_info &in) { return (in.flags & 8u) != 0; }
+
 uint64_t prefix_bytes(const aceapex_info &in)
 {
-    return HDR + 16ull * (in.n_blocks + 1ull) + ((4ull * (in.max_level + 1ull) + 15) & ~15ull);
+    const uint64_t table = has_table(in) ? ((4ull * (in.max_level + 1ull) + 15) & ~15ull) : 0;
+    return HDR + 16ull * (in.n_blocks + 1ull) + table;
 }
 
 bool info_consistent(const aceapex_info &in)
@@ -1122,6 +1380,7 @@ bool info_consistent(const aceapex_info &in)
     if ((in.decoded_bytes + B - 1) / B != in.n_blocks) return false;
     if (in.max_level >= (1u << 28) || in.comp_bytes < prefix_bytes(in)) return false;
     if (in.n_deep > in.n_seq) return false;
+    if (!has_table(in) && (in.max_level || in.n_deep)) return false;  // level fields unused without levels
     if (in.n_blocks == 0 && (in.n_seq || in.n_chunks)) return false;
     if (in.n_blocks && in.n_chunks < in.n_blocks) return false;
     return true;
@@ -1241,6 +1500,8 @@ Job make_job(const aceapex_stream &s, void *d_out, int32_t *status, ChunkDesc *c
     j.c0 = c0;
     j.b0 = b0;
     j.lv0 = lv0;
+    j.table = has_table(in) ? 1u : 0u;
+    j.derive = 0;
     return j;
 }
 
@@ -1289,6 +1550,111 @@ void build_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     g.n_seq = in.n_seq;
     g.n = 1;
     g.single = true;
+}
+
+// ---- one stream, levels derived on the device
+
+constexpr uint32_t DERIVE_TAIL = 4096;  // queued matches at or below which one workgroup runs the rest
+constexpr uint32_t DERIVE_WG_MAX = 2048;  // workgroups of a derive launch, at most
+
+struct WsDerive {
+    size_t status, cnt, chunks, blk_ok, recs, level, head, next, cur, max, q0, q1, ready, page, total;
+};
+
+WsDerive ws_derive(const aceapex_info &in)
+{
+    WsDerive w;
+    size_t o = 0;
+    const size_t m4 = 4 * (size_t)in.n_seq;
+    w.status = o; o += 256;
+    w.cnt = o; o += 256;
+    w.chunks = o; o = align256(o + sizeof(ChunkDesc) * (size_t)in.n_chunks);
+    w.blk_ok = o; o = align256(o + (size_t)in.n_blocks);
+    w.recs = o; o = align256(o + 3 * m4);
+    w.level = o; o = align256(o + m4);
+    w.head = o; o = align256(o + m4);
+    w.next = o; o = align256(o + m4);
+    w.cur = o; o = align256(o + m4);
+    w.max = o; o = align256(o + m4);
+    w.q0 = o; o = align256(o + m4);
+    w.q1 = o; o = align256(o + m4);
+    w.ready = o; o = align256(o + m4);
+    w.page = o; o = align256(o + 4 * ((size_t)(in.decoded_bytes >> 8) + 1));
+    w.total = o;
+    return w;
+}
+
+// The workspace of the stream's own decode: stored levels or derived ones.
+size_t ws_one(const aceapex_info &in) { return has_table(in) ? ws_single(in).total : ws_derive(in).total; }
+
+// Decode one stream deriving its levels on the device (see the level
+// derivation kernels); d_levels, when not null, receives each match's level
+// in stream order.  The host reads the queue length back every few levels
+// (the number of levels is found on the device), so this call returns once
+// the last level has been enqueued.
+int launch_derive(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, uint32_t *d_levels,
+                  hipStream_t st)
+{
+    const aceapex_info &in = s.info;
+    const WsDerive w = ws_derive(in);
+    Batch B;
+    memset(&B, 0, sizeof B);
+    B.one = make_job(s, d_out, d_status ? d_status : (int32_t *)(ws + w.status), (ChunkDesc *)(ws + w.chunks),
+                     ws + w.blk_ok, 0, 0, 0);
+    B.one.derive = 1;
+    B.recs = (uint32_t *)(ws + w.recs);
+    B.dlevel = d_levels ? d_levels : (uint32_t *)(ws + w.level);
+    B.dhead = (uint32_t *)(ws + w.head);
+    B.dnext = (uint32_t *)(ws + w.next);
+    B.dcur = (uint32_t *)(ws + w.cur);
+    B.dmax = (uint32_t *)(ws + w.max);
+    B.dq[0] = (uint32_t *)(ws + w.q0);
+    B.dq[1] = (uint32_t *)(ws + w.q1);
+    B.dready = (uint32_t *)(ws + w.ready);
+    B.dpage = (uint32_t *)(ws + w.page);
+    B.dcnt = (uint32_t *)(ws + w.cnt);
+    B.n_jobs = 1;
+    B.n_blocks = in.n_blocks;
+    B.n_chunks = in.n_chunks;
+    B.max_level = 0;  // the parse ranks no levels
+    B.n_seq = in.n_seq;
+    B.long_copy = LONG_COPY;
+    B.xcd_parts = XCD_PARTS;
+    const uint32_t M = in.n_seq;
+    {
+        PhaseScope ps(PH_SETUP, st);
+        hipLaunchKernelGGL(k_setup, dim3(std::max<uint32_t>(1, std::min<uint32_t>(B.n_blocks, 65535))), dim3(NT), 0,
+                           st, B);
+    }
+    if (B.n_blocks) {
+        PhaseScope ps(PH_PARSE, st);
+        launch_parse<false>(B, B.n_chunks, st);
+        if (M) hipLaunchKernelGGL(k_pages, dim3(std::min<uint32_t>(DERIVE_WG_MAX, M / NT + 1)), dim3(NT), 0, st, B);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+    if (!M) return ACEAPEX_OK;
+    PhaseScope ps(PH_LEVELS, st);
+    const uint32_t G = std::max<uint32_t>(1, std::min<uint32_t>(DERIVE_WG_MAX, (M + NT - 1) / NT));
+    for (uint32_t k = 0; k <= M;) {
+        hipLaunchKernelGGL(k_derive_scan, dim3(G), dim3(NT), 0, st, B, k);
+        hipLaunchKernelGGL(k_derive_run, dim3(G), dim3(NT), 0, st, B, k);
+        k++;
+        if (k <= 2 || k % 4 == 0) {  // the queue of level k
+            uint32_t q = 0;
+            if ((e = hipMemcpyAsync(&q, B.dcnt + DC_Q + (k & 1), 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+                (e = hipStreamSynchronize(st)) != hipSuccess)
+                return hip_fail(e);
+            if (!q) break;
+            if (q <= DERIVE_TAIL) {
+                hipLaunchKernelGGL(k_derive_tail, dim3(1), dim3(NT_TAIL), 0, st, B, k);
+                break;
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_derive_final, dim3(1), dim3(64), 0, st, B);
+    e = hipGetLastError();
+    return e == hipSuccess ? ACEAPEX_OK : hip_fail(e);
 }
 
 // ---- a batch of streams (all with host level tables), at most JOBS_MAX
@@ -1545,7 +1911,7 @@ size_t many_bytes(const aceapex_desc *d, uint32_t n)
         m = group_size(d + i, n - i);
         batched += ws_batch(d + i, m).total;
     }
-    for (uint32_t i = 0; i < n; i++) single += ws_single(d[i].s.info).total;
+    for (uint32_t i = 0; i < n; i++) single += ws_one(d[i].s.info);
     return std::max(batched, single);
 }
 
@@ -1590,6 +1956,8 @@ int enqueue_plan(const PlanImpl *p, const Tune &tn, hipStream_t st, bool timed)
 }
 
 }  // namespace
+
+void aceapex_impl::set_last_hip_error(int e) { g_last_hip = e; }
 
 // Workspace of aceapex_decode_noalloc: one library-static device array that
 // every device the library runs on holds until the process ends.  In host
@@ -1646,7 +2014,7 @@ int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info)
     in.n_deep = rd32h(h + 44);
     in.n_chunks = rd32h(h + 48);
     in.content_hash = rd64h(h + 56);
-    if ((in.flags & ~0xFu) || !(in.flags & 8u) || h[11] != 0 || rd32h(h + 52) != 0) return ACEAPEX_E_FORMAT;
+    if ((in.flags & ~0xFu) || h[11] != 0 || rd32h(h + 52) != 0) return ACEAPEX_E_FORMAT;
     if (!info_consistent(in)) return ACEAPEX_E_FORMAT;
     *info = in;
     return ACEAPEX_OK;
@@ -1657,6 +2025,7 @@ int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *cou
     aceapex_info in;
     int rc = aceapex_probe(h_stream_prefix, h_len, &in);
     if (rc) return rc;
+    if (!has_table(in)) return ACEAPEX_E_FORMAT;  // the four streams of Sec. 3.2 carry no level table
     const uint64_t at = HDR + 16ull * (in.n_blocks + 1ull), cnt = (uint64_t)in.max_level + 1;
     if (!counts || n < cnt || h_len < at + 4 * cnt) return ACEAPEX_E_INVAL;
     uint64_t sum = 0;
@@ -1680,9 +2049,28 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
 {
     int rc = check_stream_args(stream, d_out, out_capacity);
     if (rc) return rc;
-    const size_t need = ws_single(stream->info).total;
+    const size_t need = ws_one(stream->info);
     if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need) return ACEAPEX_E_WORKSPACE;
+    if (!has_table(stream->info))  // no stored levels: derived on the device
+        return launch_derive(*stream, d_out, (uint8_t *)d_workspace, d_status, nullptr, (hipStream_t)hip_stream);
     return launch_single(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream);
+}
+
+int aceapex_decode_derive(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, void *d_workspace,
+                          size_t ws_bytes, uint32_t *d_levels, int32_t *d_status, void *hip_stream)
+{
+    int rc = check_stream_args(stream, d_out, out_capacity);
+    if (rc) return rc;
+    if (((uintptr_t)d_levels & 3)) return ACEAPEX_E_INVAL;
+    const size_t need = ws_derive(stream->info).total;
+    if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need) return ACEAPEX_E_WORKSPACE;
+    return launch_derive(*stream, d_out, (uint8_t *)d_workspace, d_status, d_levels, (hipStream_t)hip_stream);
+}
+
+size_t aceapex_workspace_bytes_derive(const aceapex_info *info)
+{
+    if (!info || !info_consistent(*info)) return 0;
+    return ws_derive(*info).total;
 }
 
 int aceapex_decode_noalloc(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, int32_t *d_status,
@@ -1690,6 +2078,7 @@ int aceapex_decode_noalloc(const aceapex_stream *stream, void *d_out, uint64_t o
 {
     int rc = check_stream_args(stream, d_out, out_capacity);
     if (rc) return rc;
+    if (!has_table(stream->info)) return ACEAPEX_E_UNSUPPORTED;  // derived levels need host read-backs
     if (ws_single(stream->info).total > SCRATCH_BYTES) return ACEAPEX_E_WORKSPACE;
     uint8_t *ws = nullptr;
     if ((rc = scratch_on_device(&ws))) return rc;
@@ -1709,6 +2098,7 @@ int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspa
     for (uint32_t i = 0; i < n; i++) {
         int rc = check_stream_args(&h_descs[i].s, h_descs[i].d_out, h_descs[i].out_capacity);
         if (rc) return rc;
+        if (!has_table(h_descs[i].s.info)) return ACEAPEX_E_UNSUPPORTED;  // derived levels: one stream per call
         tables = tables && h_descs[i].s.h_levels;
     }
     if (n && (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < many_bytes(h_descs, n)))
@@ -1764,6 +2154,7 @@ int aceapex_plan_create(const aceapex_desc *h_descs, uint32_t n, void *d_workspa
     for (uint32_t i = 0; i < n; i++) {
         int rc = check_stream_args(&h_descs[i].s, h_descs[i].d_out, h_descs[i].out_capacity);
         if (rc) return rc;
+        if (!has_table(h_descs[i].s.info)) return ACEAPEX_E_UNSUPPORTED;
         if (!h_descs[i].s.h_levels) return ACEAPEX_E_INVAL;
     }
     if (n && (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < many_bytes(h_descs, n)))

@@ -395,11 +395,13 @@ void Encoder::serialize(uint64_t b)
             const Piece &m = bp.pieces[i];
             put_leb(len, m.len - o_.min_match);
             put_u32(off, m.src);
-            put_leb(lvl, (uint32_t)m.lvl);
-            bp.max_level = std::max(bp.max_level, (uint32_t)m.lvl);
-            bp.n_deep += m.lvl > 0;
-            if ((size_t)m.lvl >= bp.per_level.size()) bp.per_level.resize((size_t)m.lvl + 1, 0);
-            bp.per_level[m.lvl]++;
+            if (o_.levels) {
+                put_leb(lvl, (uint32_t)m.lvl);
+                bp.max_level = std::max(bp.max_level, (uint32_t)m.lvl);
+                bp.n_deep += m.lvl > 0;
+                if ((size_t)m.lvl >= bp.per_level.size()) bp.per_level.resize((size_t)m.lvl + 1, 0);
+                bp.per_level[m.lvl]++;
+            }
             q += m.len;
         }
     }
@@ -478,7 +480,8 @@ int64_t Encoder::run(uint8_t **result)
     for (uint64_t b = 0; b < nb_; b++)
         for (size_t l = 0; l < blk_[b].per_level.size(); l++) levels[l] += blk_[b].per_level[l];
     const uint64_t level_at = 64 + 16 * (nb_ + 1);
-    const uint64_t table = level_at + ((4 * levels.size() + 15) & ~(size_t)15);
+    // without levels (the four streams of Sec. 3.2 only) there is no level table
+    const uint64_t table = level_at + (o_.levels ? ((4 * levels.size() + 15) & ~(size_t)15) : 0);
     uint64_t total = table;
     std::vector<uint64_t> at(nb_ + 1);
     std::vector<uint32_t> seq_base(nb_ + 1), chunk_base(nb_ + 1);
@@ -499,11 +502,11 @@ int64_t Encoder::run(uint8_t **result)
     chunk_base[nb_] = n_chunks;
     uint8_t *out = (uint8_t *)calloc(total, 1);
     if (!out) return ACEAPEX_E_NOMEM;
-    memcpy(out + level_at, levels.data(), 4 * levels.size());
+    if (o_.levels) memcpy(out + level_at, levels.data(), 4 * levels.size());
     uint8_t h[64] = {0};
     memcpy(h, "ACX1", 4);
     const uint16_t version = 1;
-    uint16_t flags = 8;
+    uint16_t flags = o_.levels ? 8 : 0;
     if (o_.flatten == 1) flags |= 1;
     if (o_.flatten == 2) flags |= 2;
     if (o_.max_depth) flags |= 4;
@@ -540,7 +543,7 @@ bool opts_valid(const aceapex_enc_opts *o)
 {
     return o && o->block_log2 >= 3 && o->block_log2 <= 30 && o->min_match >= 4 && o->min_match <= 255 &&
            o->flatten <= 2 && o->chain_depth >= 1 && o->hash_bits >= 8 && o->hash_bits <= 28 &&
-           o->tiebreak <= 1 && o->chunk_log2 <= 20;
+           o->tiebreak <= 1 && o->chunk_log2 <= 20 && o->levels <= 1;
 }
 
 }  // namespace
@@ -560,6 +563,7 @@ void aceapex_enc_defaults(aceapex_enc_opts *o)
     o->chunk_log2 = 10;
     o->threads = 0;
     o->verbose = 0;
+    o->levels = 1;
 }
 
 int64_t aceapex_encode(const void *h_in, uint64_t n, const aceapex_enc_opts *opts, void **h_stream)

@@ -16,10 +16,20 @@ The loop
 `mode="fifo"` is the plain baseline: one request per launch, one at a time.
 Outputs stay resident; `keep_outputs=True` returns a host copy of each
 result for checking.
+
+Device choice (Sec. 7.2 finds a small, deep stream slower on the GPU than on
+the CPU; Sec. 8.2 suggests choosing per input): with host copies of the
+streams, `route="auto"` pre-scans each request's size and deepest level and
+sends it to the host decoder (aceapex_decode_host on a worker thread) when a
+cost model says the host finishes first.  A host-decoded result is copied
+into the same device arena, so every result ends up resident on the device;
+its latency runs to the end of that copy.
 """
 from __future__ import annotations
 
+import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -85,7 +95,31 @@ class Request:
     done: float = -1.0
     status: int = 0
     result: np.ndarray = None
+    route: str = "gpu"  # device that decoded it: "gpu" or "cpu"
     _mem: list = field(default_factory=list)
+
+
+@dataclass
+class CostModel:
+    """Estimated completion times of one request on each device.
+
+    host: size / cpu_gbps (one host thread, aceapex_decode_host).
+    GPU:  a batch's fixed cost, one level boundary per level of the stream
+          (the wavefront of Sec. 7.1 runs levels 0..max_level), and the size
+          at the batched decode rate."""
+    cpu_gbps: float = 0.4
+    gpu_gbps: float = 100.0
+    gpu_fixed_us: float = 150.0
+    gpu_level_us: float = 2.5
+
+    def cpu_s(self, n: int) -> float:
+        return n / (self.cpu_gbps * 1e9)
+
+    def gpu_s(self, n: int, levels: int) -> float:
+        return (self.gpu_fixed_us + levels * self.gpu_level_us) * 1e-6 + n / (self.gpu_gbps * 1e9)
+
+    def route(self, n: int, levels: int) -> str:
+        return "cpu" if self.cpu_s(n) < self.gpu_s(n, levels) else "gpu"
 
 
 @dataclass
@@ -105,10 +139,15 @@ class Server:
     which requests are admitted.
     """
 
-    def __init__(self, pool, budget_bytes: int, lanes: int = 4, max_batch: int = 256, device="cuda"):
+    def __init__(self, pool, budget_bytes: int, lanes: int = 4, max_batch: int = 256, device="cuda",
+                 host_streams=None, cpu_workers: int = 4, cost: CostModel | None = None):
         import torch
 
         self.pool = list(pool)
+        self.host_streams = list(host_streams) if host_streams is not None else None
+        self.cost = cost or CostModel()
+        self.cpu_workers = cpu_workers
+        self._tls = threading.local()
         self.device = device
         self.max_batch = max_batch
         self._ws_one = [max(_abi.workspace_bytes([_abi.Desc(p.abi(), None, p.n, None)]), ALIGN)
@@ -125,14 +164,71 @@ class Server:
     def need_bytes(self, stream: int) -> int:
         return (self.pool[stream].n + ALIGN - 1) // ALIGN * ALIGN
 
-    def run(self, arrivals, mode: str = "continuous", keep_outputs: bool = False, timeout_s: float = 600.0):
-        """Serve (arrival_seconds, pool_index) pairs; returns the requests."""
+    def route_of(self, stream: int, route: str) -> str:
+        """The device a request for pool stream `stream` goes to."""
+        if route == "gpu" or self.host_streams is None:
+            return "gpu"
+        if route == "cpu":
+            return "cpu"
+        d = self.pool[stream]
+        return self.cost.route(d.n, int(d.info.max_level) + 1)
+
+    def calibrate_cpu(self, max_bytes: int = 8 << 20) -> float:
+        """Measure the host decoder's rate (one thread) on the pool's streams of
+        at most max_bytes (decoded), and put it in the cost model."""
+        if self.host_streams is None:
+            return self.cost.cpu_gbps
+        picks = [i for i in range(len(self.pool)) if 0 < self.pool[i].n <= max_bytes][:8]
+        nbytes, secs = 0, 0.0
+        for i in picks:
+            out = np.empty(self.pool[i].n, dtype=np.uint8)
+            t0 = time.perf_counter()
+            rc = _abi.decode_host(self.host_streams[i], out, 1)
+            secs += time.perf_counter() - t0
+            if rc:
+                raise AceapexError(rc, "decode_host")
+            nbytes += out.size
+        if secs > 0:
+            self.cost.cpu_gbps = nbytes / secs / 1e9
+        return self.cost.cpu_gbps
+
+    def _cpu_decode(self, r: Request, view):
+        """Worker thread: decode on the host, then copy into the request's
+        arena slot on this thread's own stream; returns the status."""
         import torch
 
+        st = getattr(self._tls, "stream", None)
+        if st is None:
+            st = self._tls.stream = torch.cuda.Stream(device=self.device)
+        d = self.pool[r.stream]
+        out = np.empty(max(d.n, 1), dtype=np.uint8)
+        rc = _abi.decode_host(self.host_streams[r.stream], out[:d.n], 1)
+        if rc == 0 and d.n:
+            with torch.cuda.stream(st):
+                view[:d.n].copy_(torch.from_numpy(out[:d.n]))
+            st.synchronize()
+        return rc
+
+    def run(self, arrivals, mode: str = "continuous", keep_outputs: bool = False, timeout_s: float = 600.0,
+            route: str = "gpu"):
+        """Serve (arrival_seconds, pool_index) pairs; returns the requests.
+
+        route: "gpu" (every request on the GPU), "cpu" (every request on the
+        host decoder) or "auto" (per request, the device the cost model
+        picks); "fifo" mode always uses the GPU."""
+        import torch
+
+        if route != "gpu" and self.host_streams is None:
+            raise ValueError("host routes need host copies of the streams")
+        if mode == "fifo":
+            route = "gpu"
         reqs = [Request(i, int(s), float(t)) for i, (t, s) in enumerate(sorted(arrivals))]
         for r in reqs:
+            r.route = self.route_of(r.stream, route)
             if self.need_bytes(r.stream) > self.arena.size or self._ws_one[r.stream] > self.lane_ws:
                 raise ValueError(f"request {r.rid} needs more memory than the budget holds")
+        cpu_pool = ThreadPoolExecutor(self.cpu_workers) if any(r.route == "cpu" for r in reqs) else None
+        cpu_waiting, cpu_running = [], []
         waiting = []
         inflight = []
         nxt = 0
@@ -146,8 +242,33 @@ class Server:
             if now > timeout_s:
                 raise TimeoutError("serving run exceeded its time limit")
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
-                waiting.append(reqs[nxt])
+                (cpu_waiting if reqs[nxt].route == "cpu" else waiting).append(reqs[nxt])
                 nxt += 1
+            # host route: completed decodes, then admission (first come, first served)
+            still_cpu = []
+            for r, fut, view in cpu_running:
+                if fut.done():
+                    r.done = time.perf_counter() - t0
+                    r.status = int(fut.result())
+                    if keep_outputs:
+                        r.result = view[: self.pool[r.stream].n].cpu().numpy()
+                    for o, n in r._mem:
+                        self.arena.release(o, n)
+                    r._mem = []
+                    done_count += 1
+                else:
+                    still_cpu.append((r, fut, view))
+            cpu_running = still_cpu
+            while cpu_waiting and len(cpu_running) < self.cpu_workers:
+                r = cpu_waiting[0]
+                got = self.arena.alloc(self.need_bytes(r.stream))
+                if got is None:
+                    break
+                cpu_waiting.pop(0)
+                r._mem.append(got)
+                r.admitted = r.launched = time.perf_counter() - t0
+                view = self.arena.view(got[0], max(self.pool[r.stream].n, 1))
+                cpu_running.append((r, cpu_pool.submit(self._cpu_decode, r, view), view))
             still = []
             for b in inflight:
                 if b.event.query():
@@ -184,10 +305,12 @@ class Server:
                     self._launch(batch, lane, inflight, t0, waiting)
                     lanes_busy[lane] = True
                     continue
-            if not inflight and not waiting and nxt < len(reqs):
+            if not inflight and not waiting and not cpu_running and not cpu_waiting and nxt < len(reqs):
                 wait = reqs[nxt].arrival - (time.perf_counter() - t0)
                 if wait > 2e-4:
                     time.sleep(wait - 1e-4)
+        if cpu_pool is not None:
+            cpu_pool.shutdown(wait=True)
         torch.cuda.synchronize()
         return reqs
 
@@ -232,6 +355,9 @@ def summarize(reqs, pool) -> dict:
         "decoded_bytes": int(nbytes),
         "aggregate_gbps": float(nbytes / span / 1e9) if span > 0 else 0.0,
         "errors": int(sum(1 for r in reqs if r.status)),
+        "routes": {dev: {"requests": sum(1 for r in reqs if r.route == dev),
+                         "bytes": int(sum(pool[r.stream].n for r in reqs if r.route == dev))}
+                   for dev in ("gpu", "cpu")},
     }
 
 

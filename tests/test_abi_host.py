@@ -45,12 +45,23 @@ def test_probe_rejects_bad_headers():
     with pytest.raises(_abi.AceapexError) as e:
         _abi.probe(s[:10])
     assert e.value.code == _abi.E_INVAL
-    for i, v in [(0, ord("B")), (4, 2), (7, 0x80), (6, 0), (11, 1), (32, 99)]:
+    for i, v in [(0, ord("B")), (4, 2), (7, 0x80), (6, 0x18), (11, 1), (32, 99)]:
         bad = s.copy()
         bad[i] = v
         with pytest.raises(_abi.AceapexError) as e:
             _abi.probe(bad)
         assert e.value.code == _abi.E_FORMAT, i
+    # without the levels flag (the four streams of Sec. 3.2) the level fields must be zero
+    deep = oracle.encode(synth.markov(20_000, 2), block_log2=10)
+    assert _abi.probe(deep).max_level > 0
+    bad = deep.copy()
+    bad[6] &= 0xF7
+    with pytest.raises(_abi.AceapexError) as e:
+        _abi.probe(bad)
+    assert e.value.code == _abi.E_FORMAT
+    free = oracle.encode(synth.markov(20_000, 2), block_log2=10, levels=0)
+    info = _abi.probe(free)
+    assert info.flags & 8 == 0 and info.max_level == 0 and _abi.level_table(free, info) is None
 
 
 def test_workspace_bytes_covers_every_match_record():
@@ -58,7 +69,7 @@ def test_workspace_bytes_covers_every_match_record():
     a = oracle.encode(x, block_log2=18)
     ia = _abi.probe(a)
     wa = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia, None), 0, ia.decoded_bytes, 0)])
-    assert wa >= 12 * ia.n_seq + 48 * ia.n_chunks
+    assert wa >= 12 * ia.n_seq + 64 * ia.n_chunks
     two = _abi.workspace_bytes([_abi.Desc(_abi.Stream(0, ia, None), 0, 0, 0)] * 2)
     assert 2 * wa - 4096 <= two <= 2 * wa + 4096
 

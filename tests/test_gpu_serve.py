@@ -1,6 +1,7 @@
 """GPU checks of the serving loop: every request served under continuous
 batching decodes exactly as the same stream decoded alone, whatever the mix
-it was batched with, and a tight memory budget only delays admission."""
+it was batched with and whichever device (GPU, or the host decoder) the
+request was routed to, and a tight memory budget only delays admission."""
 import numpy as np
 import pytest
 
@@ -19,7 +20,7 @@ def pool():
     import paper_2606_04268_amd as ax
 
     rng = np.random.default_rng(77)
-    originals, streams = [], []
+    originals, streams, hosts = [], [], []
     for i in range(12):
         n = int(np.exp(rng.uniform(np.log(2_000), np.log(3_000_000))))
         x = synth.make(["markov", "fastq", "wiki", "random"][i % 4], n, 900 + i)
@@ -27,7 +28,17 @@ def pool():
                           max_depth=int(rng.choice([0, 4])))
         originals.append(x)
         streams.append(ax.to_device(s))
-    return originals, streams
+        hosts.append(s)
+    # a small stream with a deep chain: one match per level, 700 levels
+    seg = np.frombuffer(np.random.default_rng(3).integers(0, 256, 16, dtype=np.uint8).tobytes(), np.uint8)
+    x = np.concatenate([np.concatenate([np.frombuffer((i ^ 0x80808080).to_bytes(4, "little"), np.uint8), seg])
+                        for i in range(700)])
+    s = oracle.encode(x, tiebreak=1, hash_bits=12, block_log2=12)
+    assert oracle.header_fields(s)["max_level"] > 600
+    originals.append(x)
+    streams.append(ax.to_device(s))
+    hosts.append(s)
+    return originals, streams, hosts
 
 
 def alone(streams):
@@ -45,7 +56,7 @@ def alone(streams):
 def test_served_requests_match_alone(pool, mode):
     from paper_2606_04268_amd.serve import Server, poisson_arrivals, summarize
 
-    originals, streams = pool
+    originals, streams, _ = pool
     ref = alone(streams)
     for x, r in zip(originals, ref):
         assert np.array_equal(x, r)
@@ -67,7 +78,7 @@ def test_tight_budget_delays_but_serves(pool):
     all complete, first come first served."""
     from paper_2606_04268_amd.serve import Server
 
-    originals, streams = pool
+    originals, streams, _ = pool
     biggest = max(d.n for d in streams)
     # lane workspaces take twice the largest single workspace each
     from paper_2606_04268_amd import workspace_bytes
@@ -84,3 +95,29 @@ def test_tight_budget_delays_but_serves(pool):
         assert r.status == 0
         assert np.array_equal(r.result, originals[r.stream])
     assert srv.arena.used == 0
+
+
+@pytest.mark.parametrize("route", ["cpu", "auto"])
+def test_routes_give_the_same_results(pool, route):
+    """Requests routed to the host decoder, or split between the devices by
+    the cost model (size and deepest level), decode exactly as alone; the
+    host-decoded results land in the same device arena."""
+    from paper_2606_04268_amd.serve import Server, poisson_arrivals, summarize
+
+    originals, streams, hosts = pool
+    srv = Server(streams, budget_bytes=256 << 20, lanes=3, max_batch=32, host_streams=hosts, cpu_workers=3)
+    arrivals = poisson_arrivals(90, 4000.0, len(streams), seed=9)
+    say(f"[gpu] serve 90 requests route={route}")
+    reqs = srv.run(arrivals, keep_outputs=True, timeout_s=120, route=route)
+    for r in reqs:
+        assert r.status == 0
+        assert np.array_equal(r.result, originals[r.stream])
+    s = summarize(reqs, streams)
+    assert s["errors"] == 0 and srv.arena.used == 0
+    if route == "cpu":
+        assert s["routes"]["gpu"]["requests"] == 0
+    else:
+        deep = len(streams) - 1
+        assert srv.route_of(deep, "auto") == "cpu"  # 700 levels of a 14 KB stream
+        assert srv.route_of(int(np.argmax([d.n for d in streams])), "auto") == "gpu"
+        assert s["routes"]["cpu"]["requests"] > 0 and s["routes"]["gpu"]["requests"] > 0

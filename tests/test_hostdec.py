@@ -1,0 +1,102 @@
+"""The library's host (CPU) decoder, aceapex_decode_host, against the oracle:
+its output must equal the oracle's sequential decode byte for byte for every
+stream, thread count and block size, corrupt streams must be rejected or
+decoded without any write past the output, and the threads' cross-block
+waits must end (chains that cross many blocks)."""
+import numpy as np
+import pytest
+
+import oracle
+import streamgen
+import synth
+from paper_2606_04268_amd import _abi
+
+GUARD = 256
+
+
+def host_decode(s, threads):
+    n = oracle.header_fields(s)["decoded_bytes"]
+    buf = np.full(n + 2 * GUARD, 0xA5, dtype=np.uint8)
+    out = buf[GUARD:GUARD + n]
+    rc = _abi.decode_host(np.ascontiguousarray(s), out, threads)
+    assert (buf[:GUARD] == 0xA5).all() and (buf[GUARD + n:] == 0xA5).all(), "write outside the output"
+    return rc, out
+
+
+@pytest.mark.parametrize("threads", [1, 2, 7])
+@pytest.mark.parametrize("kind", ["markov", "fastq", "wiki", "random"])
+@pytest.mark.parametrize("opts", [dict(), dict(flatten=1), dict(max_depth=8), dict(flatten=2, block_log2=12),
+                                  dict(block_log2=9, chunk_log2=3)], ids=["plain", "flat", "d8", "flatlit", "small"])
+def test_matches_oracle(kind, opts, threads):
+    x = synth.make(kind, (1 << 19) + 777, 404)
+    s = oracle.encode(x, **dict(dict(block_log2=16), **opts))
+    rc, got = host_decode(s, threads)
+    assert rc == 0
+    assert np.array_equal(got, x) and np.array_equal(got, oracle.decode(s))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_token_streams(seed):
+    rng = np.random.default_rng(seed)
+    bl = [3, 5, 8, 12][seed % 4]
+    n = int(rng.integers(0, 5000))
+    blocks, lits = streamgen.random_tokens(rng, n, bl, max_len=[6, 40, 300][seed % 3])
+    s, want = streamgen.build(blocks, lits, n, block_log2=bl, chunk_log2=int(rng.integers(0, 5)),
+                              varint_width=np.random.default_rng(seed) if seed % 2 else None)
+    for t in (1, 3, 8):
+        rc, got = host_decode(s, t)
+        assert rc == 0 and got.tobytes() == want
+
+
+def test_chain_across_many_blocks():
+    """Every match copies the one before it and straddles a block edge: each
+    block waits on the previous one."""
+    m = 2000
+    blocks_tokens = [([(4, 4, 0)] + [(0, 4, 4 * i) for i in range(1, m)], 0)]
+    s1, want = streamgen.build(blocks_tokens, b"abcd", 4 + 4 * m, block_log2=16)
+    x = np.frombuffer(want, np.uint8)
+    s = oracle.encode(x, block_log2=5, tiebreak=1, hash_bits=12)
+    for t in (1, 2, 16):
+        rc, got = host_decode(s, t)
+        assert rc == 0 and np.array_equal(got, x)
+        rc, got = host_decode(s1, t)
+        assert rc == 0 and np.array_equal(got, x)
+
+
+def test_edge_cases():
+    for x in [b"", b"a", b"abcd", b"abcdabcdabcd", bytes(range(256)) * 5, b"q" * 5000]:
+        s = oracle.encode(x, block_log2=4, hash_bits=10)
+        rc, got = host_decode(s, 4)
+        assert rc == 0 and got.tobytes() == x
+
+
+def test_corrupt_streams_never_write_outside():
+    x = synth.markov(60_000, 8)
+    s = oracle.encode(x, block_log2=10, chunk_log2=3)
+    rng = np.random.default_rng(77)
+    rejected = 0
+    for _ in range(300):
+        bad = s.copy()
+        for _ in range(int(rng.integers(1, 4))):
+            i = int(rng.integers(64, s.size))
+            bad[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        try:
+            h = oracle.header_fields(bad)
+        except Exception:
+            continue
+        if h["decoded_bytes"] != x.size:
+            continue
+        rc, _ = host_decode(bad, int(rng.integers(1, 5)))
+        assert rc in (0, _abi.E_CORRUPT, _abi.E_FORMAT)
+        rejected += rc != 0
+    assert rejected > 50
+
+
+def test_overlapping_source_rejected():
+    s, _ = streamgen.build([([(4, 4, 0)], 0)], b"abcd", 8, block_log2=8)
+    bad = s.copy()
+    base = int.from_bytes(bad[64:72].tobytes(), "little")
+    off_at = base + 32 + 32
+    bad[off_at:off_at + 4] = np.frombuffer((2).to_bytes(4, "little"), np.uint8)
+    rc, _ = host_decode(bad, 1)
+    assert rc == _abi.E_CORRUPT
