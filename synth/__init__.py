@@ -55,6 +55,8 @@ def _load():
         lib.synth_uniform.restype = None
         lib.synth_raw.argtypes = [ctypes.POINTER(ctypes.c_uint64), u64, u64]
         lib.synth_raw.restype = None
+        lib.synth_raw_state.argtypes = [ctypes.POINTER(ctypes.c_uint64), u64, ctypes.POINTER(ctypes.c_uint64)]
+        lib.synth_raw_state.restype = None
         _lib = lib
     return _lib
 
@@ -99,6 +101,15 @@ def splitmix64(x: int) -> int:
 def uniform(n: int, seed: int) -> np.ndarray:
     out = np.empty(n, dtype=np.float64)
     _load().synth_uniform(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, seed)
+    return out
+
+
+def raw64_state(n: int, state) -> np.ndarray:
+    """n raw xoshiro256** outputs from the given 4-word state (for reference vectors)."""
+    st = np.ascontiguousarray(np.asarray(state, dtype=np.uint64))
+    out = np.empty(n, dtype=np.uint64)
+    _load().synth_raw_state(out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n,
+                            st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     return out
 
 

@@ -415,6 +415,14 @@ void synth_uniform(double *out, uint64_t n, uint64_t seed)
     for (uint64_t i = 0; i < n; i++) out[i] = rng_unit(&r);
 }
 
+/* n raw 64-bit outputs of xoshiro256** from the state s[0..3] as given */
+void synth_raw_state(uint64_t *out, uint64_t n, const uint64_t *state)
+{
+    rng_t r;
+    for (int i = 0; i < 4; i++) r.s[i] = state[i];
+    for (uint64_t i = 0; i < n; i++) out[i] = rng_next(&r);
+}
+
 /* n raw 64-bit outputs of xoshiro256** seeded with `seed` */
 void synth_raw(uint64_t *out, uint64_t n, uint64_t seed)
 {
