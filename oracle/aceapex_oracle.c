@@ -100,6 +100,7 @@ static void buf_reserve(buf_t *b, uint64_t extra)
 
 static void buf_put(buf_t *b, const void *src, uint64_t n)
 {
+    if (n == 0) return; /* src may be NULL for an empty section */
     buf_reserve(b, n);
     if (b->oom) return;
     memcpy(b->p + b->len, src, n);
@@ -108,6 +109,7 @@ static void buf_put(buf_t *b, const void *src, uint64_t n)
 
 static void buf_zero(buf_t *b, uint64_t n)
 {
+    if (n == 0) return;
     buf_reserve(b, n);
     if (b->oom) return;
     memset(b->p + b->len, 0, n);
@@ -654,13 +656,14 @@ static int run_block(const shdr_t *h, const sblk_t *k, exec_t *x, uint32_t b)
         if (m > k->out_end - p) return ORC_E_CORRUPT;
         if (s + m > p) return ORC_E_CORRUPT; /* source must lie entirely before the destination */
         if (levels && (lv > h->max_level || lv > k->max_level)) return ORC_E_CORRUPT;
+        /* the source bytes, and their writer levels, are read only once final */
+        if (x->wait && x->wait(x->wait_ctx, s, s + m)) return ORC_E_CORRUPT;
         if (!levels) {
             /* no stored level: the definition of Sec. 7.1 from the writers of the source bytes */
             int32_t mx = -1;
             for (uint64_t j = 0; j < m; j++) if (x->writer_lvl[s + j] > mx) mx = x->writer_lvl[s + j];
             lv = (uint32_t)(mx + 1);
         }
-        if (x->wait && x->wait(x->wait_ctx, s, s + m)) return ORC_E_CORRUPT;
         memcpy(x->out + p, x->out + s, m); /* s + m <= p: the ranges never overlap */
         if (x->writer_lvl) for (uint64_t j = 0; j < m; j++) x->writer_lvl[p + j] = (int32_t)lv;
         if (x->tok) {
