@@ -53,6 +53,10 @@
 #include "aceapex.h"
 #include "internal.h"
 
+using aceapex_impl::has_table;
+using aceapex_impl::info_consistent;
+using aceapex_impl::prefix_bytes;
+
 namespace {
 
 constexpr int NT = 256;                     // threads per workgroup
@@ -1361,30 +1365,8 @@ struct PhaseScope {
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-inline uint16_t rd16h(const uint8_t *p) { uint16_t v; memcpy(&v, p, 2); return v; }
 inline uint32_t rd32h(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
 inline uint64_t rd64h(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
-
-bool has_table(const aceapex_info &in) { return (in.flags & 8u) != 0; }
-
-uint64_t prefix_bytes(const aceapex_info &in)
-{
-    const uint64_t table = has_table(in) ? ((4ull * (in.max_level + 1ull) + 15) & ~15ull) : 0;
-    return HDR + 16ull * (in.n_blocks + 1ull) + table;
-}
-
-bool info_consistent(const aceapex_info &in)
-{
-    if (in.block_log2 < 3 || in.block_log2 > 30 || in.min_match < 1 || in.chunk_log2 > 20) return false;
-    const uint64_t B = 1ull << in.block_log2;
-    if ((in.decoded_bytes + B - 1) / B != in.n_blocks) return false;
-    if (in.max_level >= (1u << 28) || in.comp_bytes < prefix_bytes(in)) return false;
-    if (in.n_deep > in.n_seq) return false;
-    if (!has_table(in) && (in.max_level || in.n_deep)) return false;  // level fields unused without levels
-    if (in.n_blocks == 0 && (in.n_seq || in.n_chunks)) return false;
-    if (in.n_blocks && in.n_chunks < in.n_blocks) return false;
-    return true;
-}
 
 int gpu_supported(const aceapex_info &in)
 {
@@ -1994,31 +1976,6 @@ int scratch_on_device(uint8_t **at)
 }  // namespace
 
 extern "C" {
-
-int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info)
-{
-    if (!h_stream_prefix || !info || h_len < HDR) return ACEAPEX_E_INVAL;
-    const uint8_t *h = (const uint8_t *)h_stream_prefix;
-    if (memcmp(h, "ACX1", 4) != 0 || rd16h(h + 4) != 1) return ACEAPEX_E_FORMAT;
-    aceapex_info in;
-    in.flags = rd16h(h + 6);
-    in.block_log2 = h[8];
-    in.min_match = h[9];
-    in.chunk_log2 = h[10];
-    in.max_depth = rd32h(h + 12);
-    in.decoded_bytes = rd64h(h + 16);
-    in.comp_bytes = rd64h(h + 24);
-    in.n_blocks = rd32h(h + 32);
-    in.max_level = rd32h(h + 36);
-    in.n_seq = rd32h(h + 40);
-    in.n_deep = rd32h(h + 44);
-    in.n_chunks = rd32h(h + 48);
-    in.content_hash = rd64h(h + 56);
-    if ((in.flags & ~0xFu) || h[11] != 0 || rd32h(h + 52) != 0) return ACEAPEX_E_FORMAT;
-    if (!info_consistent(in)) return ACEAPEX_E_FORMAT;
-    *info = in;
-    return ACEAPEX_OK;
-}
 
 int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *counts, uint32_t n)
 {

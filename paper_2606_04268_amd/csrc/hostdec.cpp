@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "aceapex.h"
+#include "internal.h"
 
 namespace {
 
@@ -182,7 +183,7 @@ extern "C" int aceapex_decode_host(const void *h_stream, size_t len, void *h_out
     S.s = (const uint8_t *)h_stream;
     S.len = len;
     S.out = (uint8_t *)h_out;
-    S.first_block = HDR + 16ull * (in.n_blocks + 1) + pad16(4ull * (in.max_level + 1));
+    S.first_block = aceapex_impl::prefix_bytes(in);  // header, block table, level table if any
     if (S.first_block > len) return ACEAPEX_E_FORMAT;
     if (in.n_blocks == 0) return ACEAPEX_OK;
     if (rd64(S.s + HDR) != S.first_block || rd64(S.s + HDR + 16ull * in.n_blocks) != len) return ACEAPEX_E_CORRUPT;

@@ -26,7 +26,8 @@ def host_decode(s, threads):
 @pytest.mark.parametrize("threads", [1, 2, 7])
 @pytest.mark.parametrize("kind", ["markov", "fastq", "wiki", "random"])
 @pytest.mark.parametrize("opts", [dict(), dict(flatten=1), dict(max_depth=8), dict(flatten=2, block_log2=12),
-                                  dict(block_log2=9, chunk_log2=3)], ids=["plain", "flat", "d8", "flatlit", "small"])
+                                  dict(block_log2=9, chunk_log2=3), dict(levels=0), dict(levels=0, block_log2=9)],
+                         ids=["plain", "flat", "d8", "flatlit", "small", "fourstream", "fourstream_small"])
 def test_matches_oracle(kind, opts, threads):
     x = synth.make(kind, (1 << 19) + 777, 404)
     s = oracle.encode(x, **dict(dict(block_log2=16), **opts))
@@ -43,9 +44,11 @@ def test_random_token_streams(seed):
     blocks, lits = streamgen.random_tokens(rng, n, bl, max_len=[6, 40, 300][seed % 3])
     s, want = streamgen.build(blocks, lits, n, block_log2=bl, chunk_log2=int(rng.integers(0, 5)),
                               varint_width=np.random.default_rng(seed) if seed % 2 else None)
+    s4, _ = streamgen.build(blocks, lits, n, block_log2=bl, chunk_log2=int(rng.integers(0, 5)), with_levels=False)
     for t in (1, 3, 8):
-        rc, got = host_decode(s, t)
-        assert rc == 0 and got.tobytes() == want
+        for stream in (s, s4):  # with levels, and the four streams of Sec. 3.2 alone
+            rc, got = host_decode(stream, t)
+            assert rc == 0 and got.tobytes() == want
 
 
 def test_chain_across_many_blocks():
