@@ -317,6 +317,54 @@ int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceap
 /* Free the plan (NULL is ignored).  Call it once no launch is in flight. */
 void aceapex_plan_destroy(aceapex_plan *plan);
 
+/* ---------------------------------------------- entropy stage (literals) */
+
+/* tANS-coded byte buffers, the entropy stage the paper names for its streams
+ * and leaves to future work (Sec. 4.4, Sec. 8).  A container ("ACT1") holds
+ * the normalized counts of its bytes (summing to 2^table_log) and `lanes`
+ * independent lanes: byte i belongs to lane i mod lanes, so one GPU thread
+ * decodes one lane and a wave writes 64 consecutive bytes per step.  Layout:
+ *   0 "ACT1", 4 u32 n, 8 u32 table_log (8..12), 12 u32 lanes,
+ *   16 u64 container bytes, 24 u32 bitstream bytes, 28 u32 0,
+ *   32 u16 counts[256], 544 lanes x {u32 end bit, u32 initial state},
+ *   then the lanes' bits (LSB-first, each lane from the previous one's end
+ *   bit) and 8 zero bytes.
+ * Coding: the i-th table entry in symbol order sits at position (i * step)
+ * mod 2^R, step = 2^R/2 + 2^R/8 + 3; each symbol's positions, in increasing
+ * order, carry state values c_s .. 2 c_s - 1; a decoder in state x reads
+ * position x - 2^R, outputs its symbol and moves to (y << nb) + the next nb
+ * bits, nb = R - floor(log2 y), reading its lane from the end. */
+typedef struct {
+    uint64_t n;               /* decoded bytes                        */
+    uint64_t container_bytes;
+    uint32_t table_log;
+    uint32_t lanes;
+    uint32_t bitstream_bytes;
+} aceapex_tans_info;
+
+/* Parse and check a container's header and counts from a host copy of its
+ * first 544 bytes.  Pure host code.  Returns ACEAPEX_OK, ACEAPEX_E_INVAL or
+ * ACEAPEX_E_FORMAT. */
+int aceapex_tans_probe(const void *h_prefix, size_t h_len, aceapex_tans_info *info);
+
+/* Device workspace of aceapex_tans_decode (the decode table). */
+size_t aceapex_tans_workspace_bytes(const aceapex_tans_info *info);
+
+/* Decode a device-resident container (d_in, 8-byte aligned, container_bytes
+ * long) into d_out (n bytes).  The workspace (aceapex_tans_workspace_bytes,
+ * 256-byte aligned) holds the decode table, built on the device from the
+ * counts.  *d_status (required) becomes 0, or ACEAPEX_E_CORRUPT when a lane's
+ * bits or states are inconsistent; no write leaves [d_out, d_out + n) and no
+ * read leaves the container.  Asynchronous on hip_stream. */
+int aceapex_tans_decode(const void *d_in, const aceapex_tans_info *info, void *d_out, uint64_t out_capacity,
+                        void *d_workspace, size_t ws_bytes, int32_t *d_status, void *hip_stream);
+
+/* Encode h_in[0, n) (host) into a container with 2^table_log table entries
+ * and `lanes` lanes; *h_out receives a malloc'd buffer (release with
+ * aceapex_free) and the container length is returned, or a negative
+ * ACEAPEX_E_* code.  Pure host code (threads over lanes). */
+int64_t aceapex_tans_encode(const void *h_in, uint64_t n, uint32_t table_log, uint32_t lanes, void **h_out);
+
 /* ------------------------------------------------------------ host encoder */
 
 /* Encoder parameters.  The parse is greedy over hash chains of 4-byte

@@ -15,7 +15,7 @@ from ._abi import AceapexError, Info
 
 __all__ = ["AceapexError", "Info", "DeviceStream", "probe", "encode", "to_device",
            "workspace_bytes", "decode", "decode_derive", "decode_host", "decode_many", "check_status",
-           "content_hash", "Plan"]
+           "content_hash", "Plan", "tans_decode"]
 
 
 def _torch():
@@ -194,6 +194,38 @@ def decode_host(stream, threads: int = 0) -> np.ndarray:
     if rc:
         raise AceapexError(rc, "decode_host")
     return out
+
+
+def tans_decode(container, out=None, workspace=None, status=None, stream=None, device="cuda"):
+    """Decode a tANS container (entropy-coded literals) on the GPU; the
+    container is a host array (copied to the device) or a device tensor whose
+    first 544 bytes are given as ``container[1]`` in a (tensor, host prefix)
+    pair.  Returns (out, status)."""
+    torch = _torch()
+    if isinstance(container, tuple):
+        d_in, prefix = container
+    else:
+        prefix = np.ascontiguousarray(container, dtype=np.uint8)
+        d_in = torch.from_numpy(prefix).to(device)
+    info = _abi.tans_probe(prefix)
+    dev = d_in.device
+    mine = []
+    if out is None:
+        out = torch.empty(max(int(info.n), 1), dtype=torch.uint8, device=dev)
+        mine.append(out)
+    need = _abi.tans_workspace_bytes(info)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        mine.append(workspace)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+        mine.append(status)
+    _used_on(stream, mine)
+    rc = _abi.tans_decode(d_in.data_ptr(), info, out.data_ptr(), out.numel(), workspace.data_ptr(),
+                          workspace.numel(), status.data_ptr(), _stream_handle(stream))
+    if rc:
+        raise AceapexError(rc, "tans_decode")
+    return out, status
 
 
 def check_status(status) -> None:

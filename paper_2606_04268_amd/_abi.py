@@ -58,6 +58,12 @@ class Tuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TansInfo(ctypes.Structure):
+    """aceapex_tans_info."""
+    _fields_ = [("n", ctypes.c_uint64), ("container_bytes", ctypes.c_uint64), ("table_log", ctypes.c_uint32),
+                ("lanes", ctypes.c_uint32), ("bitstream_bytes", ctypes.c_uint32)]
+
+
 class AceapexError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         msg = strerror(code) if _lib is not None else str(code)
@@ -67,6 +73,7 @@ class AceapexError(RuntimeError):
 
 EXPORTS = ("aceapex_probe", "aceapex_level_table", "aceapex_workspace_bytes", "aceapex_decode", "aceapex_decode_many",
            "aceapex_decode_noalloc", "aceapex_decode_host", "aceapex_decode_derive", "aceapex_workspace_bytes_derive",
+           "aceapex_tans_probe", "aceapex_tans_workspace_bytes", "aceapex_tans_decode", "aceapex_tans_encode",
            "aceapex_strerror", "aceapex_last_hip_error", "aceapex_enc_defaults", "aceapex_encode",
            "aceapex_free", "aceapex_timing", "aceapex_timing_read", "aceapex_tuning_defaults",
            "aceapex_plan_create", "aceapex_plan_launch", "aceapex_plan_launch_graph", "aceapex_plan_set_tuning",
@@ -104,6 +111,14 @@ def load():
     lib.aceapex_decode_derive.restype = ctypes.c_int
     lib.aceapex_workspace_bytes_derive.argtypes = [ctypes.POINTER(Info)]
     lib.aceapex_workspace_bytes_derive.restype = ctypes.c_size_t
+    lib.aceapex_tans_probe.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(TansInfo)]
+    lib.aceapex_tans_probe.restype = ctypes.c_int
+    lib.aceapex_tans_workspace_bytes.argtypes = [ctypes.POINTER(TansInfo)]
+    lib.aceapex_tans_workspace_bytes.restype = ctypes.c_size_t
+    lib.aceapex_tans_decode.argtypes = [vp, ctypes.POINTER(TansInfo), vp, ctypes.c_uint64, vp, ctypes.c_size_t, vp, vp]
+    lib.aceapex_tans_decode.restype = ctypes.c_int
+    lib.aceapex_tans_encode.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(vp)]
+    lib.aceapex_tans_encode.restype = ctypes.c_int64
     lib.aceapex_decode_host.argtypes = [vp, ctypes.c_size_t, vp, ctypes.c_uint64, ctypes.c_uint32]
     lib.aceapex_decode_host.restype = ctypes.c_int
     lib.aceapex_decode_many.argtypes = [ctypes.POINTER(Desc), ctypes.c_uint32, vp, ctypes.c_size_t, vp]
@@ -298,3 +313,39 @@ def plan_tune(plan: int, hip_stream: int, reps: int) -> Tuning:
 def plan_destroy(plan: int) -> None:
     load().aceapex_plan_destroy(plan)
 
+
+def tans_probe(container) -> TansInfo:
+    import numpy as np
+
+    buf = np.ascontiguousarray(np.frombuffer(bytes(container[:544]), dtype=np.uint8))
+    info = TansInfo()
+    rc = load().aceapex_tans_probe(buf.ctypes.data, buf.size, ctypes.byref(info))
+    if rc:
+        raise AceapexError(rc, "tans_probe")
+    return info
+
+
+def tans_workspace_bytes(info: TansInfo) -> int:
+    return int(load().aceapex_tans_workspace_bytes(ctypes.byref(info)))
+
+
+def tans_decode(d_in: int, info: TansInfo, d_out: int, out_capacity: int, d_ws: int, ws_bytes: int,
+                d_status: int, hip_stream: int) -> int:
+    return load().aceapex_tans_decode(d_in, ctypes.byref(info), d_out, out_capacity, d_ws, ws_bytes, d_status,
+                                      hip_stream)
+
+
+def tans_encode(data, table_log: int = 11, lanes: int = 1024):
+    """aceapex_tans_encode on host bytes; returns the container as a uint8 numpy array."""
+    import numpy as np
+
+    x = np.ascontiguousarray(np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray) else data,
+                             dtype=np.uint8)
+    out = ctypes.c_void_p()
+    n = load().aceapex_tans_encode(x.ctypes.data if x.size else None, x.size, table_log, lanes, ctypes.byref(out))
+    if n < 0:
+        raise AceapexError(int(n), "tans_encode")
+    try:
+        return np.ctypeslib.as_array(ctypes.cast(out, ctypes.POINTER(ctypes.c_uint8)), shape=(n,)).copy()
+    finally:
+        load().aceapex_free(out)
