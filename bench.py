@@ -23,6 +23,9 @@ workload), with, in the same line:
     continuous batching against one request at a time;
   - the level-launch floor measured on a one-match-per-level chain, and the
     sync floor it implies for each plain stream ((max_level + 1) launches);
+  - the entropy stage: the FASTQ-like stream's literal bytes (its lit[]
+    sections, 132 MB, mostly quality strings) tANS-coded on the host and
+    decoded on the GPU;
   - roofline (dominant kernel group of the 1 GiB stream), and the CPU oracle
     on a bounded sample of the same text at T = 1, 2, 4, 8, 16 threads with
     the host's memcpy bandwidth at the same T.
@@ -32,6 +35,7 @@ Other modes (one JSON line each):
   --mode plain    one plain workload (--workload), as the main entry above
   --mode batched  the batched entry alone
   --mode served   the served entry with a sweep of offered loads
+  --mode entropy  the entropy stage alone on one workload's literals (--workload)
   --mode sweep    depth limit D (1, 2, 10, unlimited) x chain flattening (off,
                   R1, R2) on wiki-like text and FASTQ-like data (32 MiB each):
                   ratio, deepest level and decoded GB/s (Sec. 7.4, Table 5)
@@ -564,6 +568,53 @@ def measure_served(args, loads, warm_requests=300, measured_requests=3000, level
     return info, rows
 
 
+# ------------------------------------------------------------------ entropy stage
+
+
+def measure_entropy(stream, name, args):
+    """The tANS stage on the literal stream of a workload: host-encoded with
+    2^11 table entries and one lane per ~512 literals, decoded on the GPU
+    (table build + lane decode), checked byte for byte.  GB/s counts the
+    decoded literal bytes."""
+    import numpy as np
+    import torch
+
+    import paper_2606_04268_amd as ax
+    from paper_2606_04268_amd import _abi
+    from paper_2606_04268_amd.stats import literals
+
+    lit = literals(stream)
+    lanes = int(min(1 << 20, max(1, lit.size // 512)))
+    t0 = time.perf_counter()
+    c = _abi.tans_encode(lit, 11, lanes)
+    enc_s = time.perf_counter() - t0
+    p = np.bincount(lit, minlength=256).astype(np.float64) / max(1, lit.size)
+    h0 = float(-(p[p > 0] * np.log2(p[p > 0])).sum())
+    dev = torch.device("cuda:0")
+    d_in = torch.from_numpy(c).to(dev)
+    ref = torch.from_numpy(lit).to(dev)
+    info = _abi.tans_probe(c)
+    out = torch.empty(max(lit.size, 1), dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(_abi.tans_workspace_bytes(info), 256), dtype=torch.uint8, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream_ = torch.cuda.current_stream(dev)
+
+    def step():
+        ax.tans_decode((d_in, c[:544]), out=out, workspace=ws, status=status, stream=stream_)
+
+    step()
+    torch.cuda.synchronize()
+    ax.check_status(status)
+    exact = bool(torch.equal(out[:lit.size], ref))
+    assert exact, f"{name}: tANS decode differs from the literals"
+    ms = _timed(step, args.steps, 2, stream_)
+    ax.check_status(status)
+    return {"workload": f"lit[] of the {name} stream", "literal_bytes": int(lit.size), "container_bytes": int(c.size),
+            "bits_per_byte": round(8 * c.size / max(1, lit.size), 3), "order0_entropy_bits": round(h0, 3),
+            "table_log": 11, "lanes": lanes, "ms_per_decode": round(ms, 4),
+            "gbps": round(lit.size / (ms * 1e-3) / 1e9, 2), "bit_exact": exact, "host_encode_s": round(enc_s, 2)}
+
+
 # ------------------------------------------------------------------ modes
 
 
@@ -579,7 +630,10 @@ def run_full(args):
     gc.collect()
     others = {}
     for name in ("markov4", "fastq256"):
-        others[name], _, _ = measure_plain(name, args)
+        others[name], s_other, _ = measure_plain(name, args)
+        if name == "fastq256":
+            entropy = measure_entropy(s_other, name, args)
+        del s_other
     cpu = None if args.no_cpu else cpu_baseline(
         sample, WORKLOADS["wiki1g"]["enc"],
         f"the first {args.cpu_sample_mib} MiB of the same wiki-like text, encoded the same way")
@@ -616,6 +670,7 @@ def run_full(args):
     }
     line["depth_limited"] = d8
     line["configs"] = others
+    line["entropy_stage"] = entropy
     if batched:
         line["batched"] = batched
     if served:
@@ -638,6 +693,22 @@ def run_plain(args):
         n = min(x.size, args.cpu_sample_mib << 20)
         line["cpu_baseline"] = cpu_baseline(x[:n].copy(), WORKLOADS[args.workload]["enc"],
                                             f"the first {n >> 20} MiB of the same input, encoded the same way")
+    print(json.dumps(line), flush=True)
+
+
+def run_entropy(args):
+    import synth
+    import paper_2606_04268_amd as ax
+
+    wl = WORKLOADS[args.workload]
+    x = synth.make(wl["kind"], wl["size"], wl["seed"])
+    s = ax.encode(x, threads=HOST_THREADS, **wl["enc"])
+    del x
+    e = measure_entropy(s, args.workload, args)
+    line = base_line(e["gbps"], args.steps, 2, e["ms_per_decode"])
+    line["metric"] = "tANS-decoded literal GB/s"
+    line["config"] = {"workload": e["workload"]}
+    line["entropy_stage"] = e
     print(json.dumps(line), flush=True)
 
 
@@ -737,7 +808,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="full", choices=["full", "plain", "batched", "served", "sweep", "algorithmic"])
+    ap.add_argument("--mode", default="full", choices=["full", "plain", "batched", "served", "sweep", "algorithmic", "entropy"])
     ap.add_argument("--workload", default="wiki1g", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plan", action="store_true", help="plain mode: skip the plan + graph leg")
@@ -757,7 +828,7 @@ def main():
               "with no communication", file=sys.stderr)
         sys.exit(2)
     {"full": run_full, "plain": run_plain, "batched": run_batched, "served": run_served, "sweep": run_sweep,
-     "algorithmic": print_algorithmic}[args.mode](args)
+     "algorithmic": print_algorithmic, "entropy": run_entropy}[args.mode](args)
 
 
 if __name__ == "__main__":

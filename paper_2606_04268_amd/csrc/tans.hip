@@ -39,9 +39,9 @@ namespace {
 
 constexpr uint32_t TH = 32, TC = 512;     // header and counts bytes
 constexpr uint32_t R_MIN = 8, R_MAX = 12;  // table sizes 256 .. 4096 entries
-constexpr int NTT = 256;                   // threads of the tANS kernels
+constexpr int NTT = 256;                   // threads of the lane decoder
+constexpr int NTB = 1024;                  // threads of the table build (four per symbol)
 
-typedef uint64_t u64u_t __attribute__((aligned(1)));
 
 __host__ __device__ inline uint32_t rd32(const uint8_t *p)
 {
@@ -59,27 +59,34 @@ struct TansArgs {
     uint32_t n, R, lanes, bs_bytes;
 };
 
-// One workgroup: the decode table from the counts.  The spread is computed in
-// parallel; the state values are then dealt out position by position.
-__global__ void __launch_bounds__(NTT) k_tans_table(TansArgs A)
+// One workgroup of NTB threads: the decode table from the counts.  Symbol
+// ranges come from a scan of the counts and the spread from a binary search
+// per table entry.  State values are then dealt in position order without a
+// serial pass: thread (q, s) counts symbol s in quarter q of the positions,
+// the counts of the quarters before q give the state value its first
+// occurrence in quarter q takes, and a second pass writes the quarter's
+// entries of s in increasing position order.
+__global__ void __launch_bounds__(NTB) k_tans_table(TansArgs A)
 {
-    __shared__ uint32_t cnt[256], cum[257], nxt[256];
-    __shared__ uint8_t sym[1u << R_MAX];
+    __shared__ uint32_t cnt[256], cum[257], inq[4][256];
+    __shared__ uint32_t symw[(1u << R_MAX) / 4];  // the spread, four symbols per word
     const uint32_t t = threadIdx.x, L = 1u << A.R, step = (L >> 1) + (L >> 3) + 3;
-    cnt[t] = A.in[TH + 2 * t] | ((uint32_t)A.in[TH + 2 * t + 1] << 8);
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        for (uint32_t s = 0; s < 256; s++) {
-            cum[s] = acc;
-            acc += cnt[s];
-        }
-        cum[256] = acc;
+    if (t < 256) {
+        cnt[t] = A.in[TH + 2 * t] | ((uint32_t)A.in[TH + 2 * t + 1] << 8);
+        cum[t + 1] = cnt[t];
     }
+    if (t == 0) cum[0] = 0;
     __syncthreads();
+    for (uint32_t d = 1; d < 256; d <<= 1) {  // inclusive scan of cum[1..256]
+        const uint32_t v = (t < 256 && t >= d) ? cum[t + 1 - d] : 0;
+        __syncthreads();
+        if (t < 256) cum[t + 1] += v;
+        __syncthreads();
+    }
     if (t == 0) *A.status = (A.n && cum[256] != L) ? ACEAPEX_E_CORRUPT : 0;  // the decode's status starts here
     if (cum[256] != L) return;
-    for (uint32_t i = t; i < L; i += NTT) {
+    uint8_t *sym = (uint8_t *)symw;
+    for (uint32_t i = t; i < L; i += NTB) {
         uint32_t lo = 0, hi = 255;  // the symbol whose cumulative range holds i
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
@@ -87,18 +94,43 @@ __global__ void __launch_bounds__(NTT) k_tans_table(TansArgs A)
         }
         sym[(uint32_t)(((uint64_t)i * step) & (L - 1))] = (uint8_t)lo;
     }
-    nxt[t] = cnt[t];
     __syncthreads();
-    if (t == 0) {
-        for (uint32_t p = 0; p < L; p++) {
-            const uint32_t s = sym[p], y = nxt[s]++;
+    const uint32_t s = t & 255, q = t >> 8, W = L / 16;  // words per quarter
+    uint32_t c = 0;
+    for (uint32_t w = q * W; w < (q + 1) * W; w++) {
+        const uint32_t x = symw[w] ^ (s * 0x01010101u);  // zero bytes where the symbol is s
+        c += ((x & 0xffu) == 0) + ((x & 0xff00u) == 0) + ((x & 0xff0000u) == 0) + ((x >> 24) == 0);
+    }
+    inq[q][s] = c;
+    __syncthreads();
+    uint32_t y = cnt[s];
+    for (uint32_t k = 0; k < q; k++) y += inq[k][s];
+    for (uint32_t w = q * W; w < (q + 1) * W; w++) {
+        const uint32_t x = symw[w] ^ (s * 0x01010101u);
+        if ((x & 0xffu) && (x & 0xff00u) && (x & 0xff0000u) && (x >> 24)) continue;
+        for (uint32_t k = 0; k < 4; k++) {
+            if ((x >> (8 * k)) & 0xffu) continue;
             const uint32_t nb = A.R - (31 - __clz(y));
-            A.table[p] = s | (nb << 8) | ((y << nb) << 13);
+            A.table[4 * w + k] = s | (nb << 8) | ((y << nb) << 13);
+            y++;
         }
     }
 }
 
-// One thread per lane: the table in LDS, the lane's bits read backwards.
+// The 32 bits at bit offset b (a multiple of 32) of the lane bits; zero
+// before the start.
+__device__ __forceinline__ uint64_t bits32(const uint8_t *bits, int64_t b)
+{
+    return b < 0 ? 0 : (uint64_t)*(const uint32_t *)(bits + (b >> 3));
+}
+
+// One thread per lane: the table in LDS, the lane's bits read backwards
+// through a 64-bit window held in registers.  The window covers bits
+// [wpos, wpos + 64) with wpos a multiple of 32 and at least 32 bits of it
+// below the read position, so every read of at most R <= 12 bits comes from
+// the window; a read that leaves fewer than 32 bits below the position slides
+// the window down by one aligned 32-bit word.  Reads past the end of the
+// last lane fall in the container's 8 bytes of slack.
 __global__ void __launch_bounds__(NTT) k_tans(TansArgs A)
 {
     __shared__ uint32_t T[1u << R_MAX];
@@ -117,22 +149,27 @@ __global__ void __launch_bounds__(NTT) k_tans(TansArgs A)
         return;
     }
     const uint32_t cnt = A.n > lane ? (A.n - lane + A.lanes - 1) / A.lanes : 0;
-    uint64_t pos = end;
+    int64_t pos = (int64_t)end;
+    int64_t wpos = ((pos >> 5) << 5) - 32;
+    uint64_t win = bits32(bits, wpos) | (bits32(bits, wpos + 32) << 32);
     uint8_t *o = A.out + lane;
     bool bad = false;
     for (uint32_t j = 0; j < cnt; j++) {
         const uint32_t e = T[st - L];
         o[(uint64_t)j * A.lanes] = (uint8_t)e;
         const uint32_t nb = (e >> 8) & 31;
-        if (pos - start < nb) {
+        if (pos - (int64_t)start < (int64_t)nb) {
             bad = true;
             break;
         }
         pos -= nb;
-        const uint64_t v = *(const u64u_t *)(bits + (pos >> 3)) >> (pos & 7);
-        st = (e >> 13) + (uint32_t)(v & ((1u << nb) - 1));
+        st = (e >> 13) + ((uint32_t)(win >> (uint32_t)(pos - wpos)) & ((1u << nb) - 1));
+        if (pos - wpos < 32) {
+            wpos -= 32;
+            win = (win << 32) | bits32(bits, wpos);
+        }
     }
-    if (bad || pos != start || st != L) atomicCAS(A.status, 0, ACEAPEX_E_CORRUPT);
+    if (bad || pos != (int64_t)start || st != L) atomicCAS(A.status, 0, ACEAPEX_E_CORRUPT);
 }
 
 }  // namespace
@@ -185,7 +222,7 @@ int aceapex_tans_decode(const void *d_in, const aceapex_tans_info *info, void *d
     A.R = info->table_log;
     A.lanes = info->lanes;
     A.bs_bytes = info->bitstream_bytes;
-    hipLaunchKernelGGL(k_tans_table, dim3(1), dim3(NTT), 0, st, A);
+    hipLaunchKernelGGL(k_tans_table, dim3(1), dim3(NTB), 0, st, A);
     hipLaunchKernelGGL(k_tans, dim3((info->lanes + NTT - 1) / NTT), dim3(NTT), 0, st, A);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

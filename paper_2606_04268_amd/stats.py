@@ -27,13 +27,30 @@ def _pad(v: int) -> int:
     return (v + 15) // 16 * 16
 
 
+def literals(stream) -> np.ndarray:
+    """The lit[] sections of every block, concatenated in stream order: the
+    literal bytes in output order (Sec. 3.2)."""
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    info = _abi.probe(s)
+    nb = info.n_blocks
+    offs = s[64:64 + 16 * (nb + 1)].view(np.uint64).reshape(-1, 2)[:, 0].astype(np.int64)
+    parts = []
+    for b in range(nb):
+        o = int(offs[b])
+        ns, nl, nc, _, cb, lb, vb, _ = (int(v) for v in s[o:o + 32].view(np.uint32))
+        at = o + 32 + 32 * nc + _pad(4 * ns) + _pad(cb) + _pad(lb) + _pad(vb)
+        parts.append(s[at:at + nl])
+    return np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+
+
 def stream_stats(stream) -> dict:
     s = np.ascontiguousarray(stream, dtype=np.uint8)
     info = _abi.probe(s)
     nb = info.n_blocks
     table = s[64:64 + 16 * (nb + 1)].view(np.uint64).reshape(-1, 2)
     offs = table[:, 0].astype(np.int64)
-    sec = dict(header=64 + 16 * (nb + 1) + _pad(4 * (info.max_level + 1)), block_headers=0, chunk_index=0, off=0, cmd=0, len=0, lvl=0,
+    table_bytes = _pad(4 * (info.max_level + 1)) if info.flags & 8 else 0  # level table, when levels are stored
+    sec = dict(header=64 + 16 * (nb + 1) + table_bytes, block_headers=0, chunk_index=0, off=0, cmd=0, len=0, lvl=0,
                lit=0, padding=0)
     lens, lvls = [], []
     lit_bytes = 0
