@@ -148,6 +148,7 @@ constexpr uint32_t DC_READY = 2;  // [2] matches ready, by level parity
 constexpr uint32_t DC_DONE = 4;   // matches run
 constexpr uint32_t DC_LEVELS = 5; // levels run (highest level + 1)
 constexpr uint32_t DC_N = 8;
+constexpr uint32_t NO_RANGE = 0xffffffffu;  // k_level: read the level's slot range on the device
 
 // Signature of a level table: the sum over levels k of a 64-bit mix of
 // (k, count_k) (the SplitMix64 finalizer).  The single-stream decode sizes its
@@ -1042,11 +1043,24 @@ __global__ void __launch_bounds__(NT) k_seal(Batch B)
 // workgroups of an XCD sweep its part together, tile after tile, so that the
 // destinations and sources they touch at one time share its L2.  Workgroup i
 // works on part i % P, which keeps each part on one XCD.
+//
+// The slots [lo, hi) come from the host's level table as kernel arguments,
+// so that no dependent load stands before the first record fetch (lo =
+// NO_RANGE: read them from the workspace).  In a batch every slot was filled
+// or sealed by k_seal.  A single stream has no seal pass: workgroup 0 of its
+// first level launch (check != 0) compares every level's fill cursor with
+// the level's end and fails the decode when a slot was left unfilled, which
+// only a corrupt stream can do; such a slot's stale record is still bounds-
+// checked like any other.
 template <bool BATCH, uint32_t R>
-__global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k)
+__global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k, uint32_t lo, uint32_t hi, uint32_t check)
 {
-    uint32_t R0, R1;
-    level_range(B, k, R0, R1);
+    uint32_t R0 = lo, R1 = hi;
+    if (lo == NO_RANGE) level_range(B, k, R0, R1);
+    if (!BATCH && check && blockIdx.x == 0) {
+        for (uint32_t i = threadIdx.x; i <= B.one.max_level; i += NT)
+            if (B.cursor[i] != B.rec_hi[i]) fail(B.one, ACEAPEX_E_CORRUPT);
+    }
     const uint32_t G = gridDim.x, P = G < B.xcd_parts ? G : B.xcd_parts;
     const uint32_t x = blockIdx.x % P, w = blockIdx.x / P, W = (G - x + P - 1) / P;
     const uint64_t S = R1 > R0 ? R1 - R0 : 0;
@@ -1402,17 +1416,22 @@ uint32_t level_wgs(uint64_t records, uint32_t per_thread, const Tune &tn)
 }
 
 template <bool BATCH>
-void launch_level(const Batch &B, uint32_t k, uint64_t cnt, const Tune &tn, hipStream_t st)
+void launch_level(const Batch &B, uint32_t k, uint64_t cnt, uint32_t lo, uint32_t hi, uint32_t check, const Tune &tn,
+                  hipStream_t st)
 {
     if (cnt <= (uint64_t)tn.level_wg_max * NT)
-        hipLaunchKernelGGL((k_level<BATCH, 1>), dim3(level_wgs(cnt, 1, tn)), dim3(NT), 0, st, B, k);
+        hipLaunchKernelGGL((k_level<BATCH, 1>), dim3(level_wgs(cnt, 1, tn)), dim3(NT), 0, st, B, k, lo, hi, check);
     else
-        hipLaunchKernelGGL((k_level<BATCH, ROUND_LEVEL>), dim3(level_wgs(cnt, ROUND_LEVEL, tn)), dim3(NT), 0, st, B, k);
+        hipLaunchKernelGGL((k_level<BATCH, ROUND_LEVEL>), dim3(level_wgs(cnt, ROUND_LEVEL, tn)), dim3(NT), 0, st, B, k,
+                           lo, hi, check);
 }
 
 // Level launches: one per level with records, sized to its count, and the
 // deep levels that hold few matches together in the tail workgroup.  counts
-// is null when the host does not know them (full-size launch per level).
+// is null when the host does not know them (full-size launch per level, slot
+// ranges read on the device); otherwise level k's slots are [sum of counts
+// below k, that sum + counts[k]), the layout k_setup (single stream) and the
+// batch layout build.
 template <typename C>
 void launch_levels(const Batch &B, const C *counts, uint64_t n_seq, const Tune &tn, hipStream_t st, bool timed)
 {
@@ -1422,13 +1441,18 @@ void launch_levels(const Batch &B, const C *counts, uint64_t n_seq, const Tune &
         while (tail > 1 && counts[tail - 1] <= tn.tail_level_max) tail--;
         if (B.max_level + 1 - tail < 2) tail = B.max_level + 1;
     }
+    uint64_t at = 0;
+    uint32_t check = 1;
     for (uint32_t k = 0; k < tail; k++) {
         const uint64_t cnt = counts ? counts[k] : n_seq;
+        const uint32_t lo = counts ? (uint32_t)at : NO_RANGE, hi = counts ? (uint32_t)(at + cnt) : 0;
+        at += counts ? cnt : 0;
         if (counts && !cnt) continue;
         if (B.jobs)
-            launch_level<true>(B, k, cnt, tn, st);
+            launch_level<true>(B, k, cnt, lo, hi, 0, tn, st);
         else
-            launch_level<false>(B, k, cnt, tn, st);
+            launch_level<false>(B, k, cnt, lo, hi, counts ? check : 0, tn, st);
+        check = 0;
     }
     if (tail <= B.max_level) {
         if (B.jobs)
