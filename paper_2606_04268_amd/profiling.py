@@ -33,6 +33,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "aceapex.hip")
 GIB_KIB = 1 << 20  # counters are reported in KiB
 
+EDGE = 12  # level launches of a deep stream listed one by one at each end
+GRID_BANDS = (1 << 20, 1 << 18, 1 << 16, 1 << 14, 0)  # grid-size bands of the other level launches
 GROUP_OF = {"k_map": "setup", "k_setup": "setup", "k_parse": "parse", "k_level": "levels", "k_tail": "levels"}
 
 
@@ -161,7 +163,7 @@ def trace(args):
         stats = list(csv.DictReader(f))
     with open(os.path.join(args.dir, "run_kernel_trace.csv")) as f:
         rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
-    lines = [f"# Kernel trace: {args.title}", "", f"Workload: {args.workload}", "",
+    lines = [f"# {args.title}", "", f"Workload: {args.workload}", "",
              "Command (from the repository root):", "", "```"] + args.command + ["```", "",
              "## Per-kernel statistics over the run", "",
              "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share of GPU time |", "|---|---|---|---|---|---|"]
@@ -179,17 +181,40 @@ def trace(args):
             seq.append(r)
         t0 = int(seq[0]["Start_Timestamp"])
         lines += ["", "## The last decode, kernel by kernel", "",
-                  "Start times are relative to `k_setup`; gaps between kernels include the profiler's own.", "",
+                  "Start times are relative to `k_setup`; gaps between kernels include the profiler's own.",
+                  f"With more than {2 * EDGE} level launches, the first and last {EDGE} are listed one by one and",
+                  "the others in bands of grid size (work-items per launch).", "",
                   "| Kernel | Grid (work-items) | Start (us) | Duration (us) |", "|---|---|---|---|"]
+        levels = [i for i, r in enumerate(seq) if _short(r["Kernel_Name"]) == "k_level"]
+        banded = set(levels[EDGE:-EDGE]) if len(levels) > 2 * EDGE else set()
+        bands = {}
         lvl = 0
-        for r in seq:
+        for i, r in enumerate(seq):
             k = _short(r["Kernel_Name"])
             a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
             label = _label(r["Kernel_Name"])
             if k == "k_level":
+                if i in banded:
+                    g = int(r["Grid_Size_X"])
+                    key = (label, next(lo for lo in GRID_BANDS if g >= lo))
+                    bands.setdefault(key, []).append((lvl, b - a))
+                    if i == max(banded):
+                        for (bl, lo), v in sorted(bands.items(), key=lambda kv: kv[1][0][0]):
+                            tot = sum(d for _, d in v)
+                            lines.append(f"| {bl}, {len(v)} launches between launch {v[0][0]} and {v[-1][0]} | "
+                                         f">= {lo} | | {tot / 1e3:.1f} in all, {tot / len(v) / 1e3:.1f} each |")
+                    lvl += 1
+                    continue
                 label = f"{label} (launch {lvl})"
                 lvl += 1
             lines.append(f"| {label} | {r['Grid_Size_X']} | {(a - t0) / 1e3:.1f} | {(b - a) / 1e3:.1f} |")
+        grp = {}
+        for r in seq:
+            g = GROUP_OF.get(_short(r["Kernel_Name"]))
+            if g:
+                grp[g] = grp.get(g, 0) + int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        lines += ["", "Kernel time of the last decode by group: " +
+                  ", ".join(f"{g} {v / 1e3:.1f} us" for g, v in grp.items()) + "."]
         total = (int(seq[-1]["End_Timestamp"]) - t0) / 1e3
         lines += ["", f"First kernel start to last kernel end: {total:.1f} us."]
     with open(args.out, "w") as f:
