@@ -142,6 +142,8 @@ struct Batch {
 };
 
 constexpr uint32_t NONE = 0xffffffffu;
+constexpr uint32_t NO_SLOT = 0xffffffffu;  // k_parse: a level whose slots ran out
+
 // counters of the derive path
 constexpr uint32_t DC_Q = 0;      // [2] matches queued to scan, by level parity
 constexpr uint32_t DC_READY = 2;  // [2] matches ready, by level parity
@@ -187,19 +189,32 @@ __device__ __forceinline__ void copy_bytes(uint8_t *d, const uint8_t *s, uint32_
     if (n & 1) *d = *s;
 }
 
-// Store the first n (1..16) bytes of lo:hi at d with exact unaligned stores.
+// Store the first n (1..16) bytes of lo:hi at d with at most two unaligned
+// stores that touch exactly those bytes: a head and a tail of the same width
+// that overlap when n is not a power of two (both carry the bytes' own
+// values), so that every length from 4 to 16 costs one or two requests.
 __device__ __forceinline__ void store_upto16(uint8_t *d, uint64_t lo, uint64_t hi, uint32_t n)
 {
     if (n >= 8) {
+        if (n == 16) {
+            u128u v;
+            v.a = (uint32_t)lo; v.b = (uint32_t)(lo >> 32); v.c = (uint32_t)hi; v.d = (uint32_t)(hi >> 32);
+            *(u128u *)d = v;
+            return;
+        }
+        const uint32_t k = 8 * (n - 8);  // bits of lo:hi below the tail
+        const uint64_t tail = k ? (lo >> k) | (hi << (64 - k)) : lo;
         *(u64u *)d = lo;
-        d += 8;
-        lo = hi;
-        n -= 8;
-        if (n == 8) { *(u64u *)d = lo; return; }
+        *(u64u *)(d + n - 8) = tail;
+    } else if (n >= 4) {
+        *(u32u *)d = (uint32_t)lo;
+        *(u32u *)(d + n - 4) = (uint32_t)(lo >> (8 * (n - 4)));
+    } else if (n >= 2) {
+        *(u16u *)d = (uint16_t)lo;
+        *(u16u *)(d + n - 2) = (uint16_t)(lo >> (8 * (n - 2)));
+    } else {
+        *d = (uint8_t)lo;
     }
-    if (n & 4) { *(u32u *)d = (uint32_t)lo; d += 4; lo >>= 32; }
-    if (n & 2) { *(u16u *)d = (uint16_t)lo; d += 2; lo >>= 16; }
-    if (n & 1) *d = (uint8_t)lo;
 }
 
 // Whole-wave copy of one long range: lane i moves the 16-byte pieces i, i+64, ...
@@ -637,6 +652,18 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
 
 // --------------------------------------------------------------- k_parse
 
+// Set the bits of the 16-byte tile segments that tile bytes [a, a + n)
+// (n > 0) touch.
+__device__ __forceinline__ void mark_segments(uint32_t *seg, uint32_t a, uint32_t n)
+{
+    const uint32_t s0 = a >> 4, s1 = (a + n - 1) >> 4;
+    for (uint32_t w = s0 >> 5; w <= (s1 >> 5); w++) {
+        const uint32_t lo = max(s0, w << 5) & 31, hi = min(s1, (w << 5) + 31) & 31;
+        const uint32_t upto = hi == 31 ? 0xffffffffu : ((2u << hi) - 1);
+        atomicOr(&seg[w], upto & ~((1u << lo) - 1));
+    }
+}
+
 // k_parse comes in three LDS shapes, picked by the deepest level of the
 // launch: LH levels are ranked in LDS (deeper ones take one global atomic per
 // match), and up to STAGE bytes of a chunk's literals are staged in LDS.  Each
@@ -652,6 +679,7 @@ struct ParseLds {
         uint8_t tile[TILE_BYTES];      // after the scan: the chunk's output span, literals in place
     } u;
     uint32_t stage[STAGE / 4 + 8];  // the chunk's literal bytes from a 16-byte boundary (+ read slack)
+    uint32_t seg[TILE_BYTES / 512];  // tile 16-byte segments that hold literal bytes, one bit each
     uint32_t lcount[LH];         // matches of the chunk per level (levels < LH)
     uint32_t lbase[LH];          // record slot reserved for them
     uint64_t tmp[NT / 64];
@@ -681,6 +709,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     }
     if (t == 0) L.bad = 0;
     for (uint32_t i = t; i < nl; i += NT) L.lcount[i] = 0;
+    if (t < TILE_BYTES / 512) L.seg[t] = 0;
     __syncthreads();
     if (c >= j.n_chunks) return;
     const ChunkDesc d = j.chunks[c];
@@ -695,9 +724,10 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     const uint32_t e0 = t * PER;
 
     // Literal placement.  When the chunk's output span fits the LDS tile, the
-    // runs are placed in the tile and the whole span is written with aligned
+    // runs are placed in the tile and the span is written with aligned
     // 16-byte stores (its match bytes are written later by the level
-    // launches).  With matches of at least 3 bytes between runs, no 4-byte
+    // launches; in chunks dense in literals, segments of match bytes only
+    // are not written at all).  With matches of at least 3 bytes between runs, no 4-byte
     // word of the output holds literal bytes of two runs, so a run is placed
     // as the whole aligned words that cover it; their other bytes lie in the
     // neighbouring matches.  The chunk's literal bytes, from the 16-byte
@@ -807,6 +837,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
         cw[u] = ce[u] = cq[u] = 0;
+        if (r[u] && tiled) mark_segments(L.seg, pos - base16, r[u]);
         if (r[u] && staged) {
             const uint32_t a0 = pos - base16;
             cw[u] = a0 & ~3u;
@@ -913,6 +944,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     }
     if (rt) {  // the trailing run of a full chunk, copied by the whole workgroup
         const uint32_t at = d.out_base + d.out_len - rt;
+        if (tiled && t == 0) mark_segments(L.seg, at - base16, rt);
         const uint8_t *ls = j.comp + d.lit_at + (d.lit_n - rt);
         for (uint32_t o = 16 * t; o < rt; o += 16 * NT) {
             const uint32_t n = min(16u, rt - o);
@@ -929,7 +961,13 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     if (tiled) {
         __syncthreads();
         const uint32_t nseg = (span_end - base16 + 15) / 16;
+        // Segments of match bytes only are skipped in chunks of at least a
+        // quarter literals.  In chunks of sparse literals writing the whole
+        // span measured faster on deep streams (the span's stores space out
+        // the workgroups' level atomics) and no slower elsewhere.
+        const bool sparse_skip = 4ull * d.lit_n >= d.out_len;
         for (uint32_t i = t; i < nseg; i += NT) {
+            if (sparse_skip && !((L.seg[i >> 5] >> (i & 31)) & 1u)) continue;  // match bytes only
             const uint32_t a = base16 + 16 * i;
             const uint8_t *tsrc = L.u.tile + 16 * i;
             if (a >= d.out_base && a + 16 <= span_end) {
@@ -987,14 +1025,32 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
         }
     }
     __syncthreads();
-    for (uint32_t i = t; i < nl; i += NT)
-        if (L.lcount[i]) L.lbase[i] = atomicAdd(&B.cursor[j.lv0 + i], L.lcount[i]);
+    // one global atomic per level present in the chunk, all issued before
+    // any returns; a level whose reserved slots would pass its end (more
+    // matches than the level table announced) gets no records
+    {
+        constexpr uint32_t NI = (LH + NT - 1) / NT;
+        uint32_t got[NI], cap[NI];
+#pragma unroll
+        for (uint32_t k = 0; k < NI; k++) {
+            const uint32_t i = t + k * NT;
+            const uint32_t c = i < nl ? L.lcount[i] : 0u;
+            got[k] = c ? atomicAdd(&B.cursor[j.lv0 + i], c) : 0u;
+            cap[k] = c ? B.rec_hi[j.lv0 + i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < NI; k++) {
+            const uint32_t i = t + k * NT;
+            if (i < nl && L.lcount[i]) L.lbase[i] = got[k] + L.lcount[i] <= cap[k] ? got[k] : NO_SLOT;
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < PER; u++) {
         if (rank[u] == 0xffffffffu) continue;
-        const uint32_t slot = L.lbase[l[u]] + rank[u];
-        if (slot >= B.rec_hi[j.lv0 + l[u]]) {  // more matches than the level table announced
+        const uint32_t lb = L.lbase[l[u]];
+        const uint32_t slot = lb + rank[u];
+        if (lb == NO_SLOT) {
             bad = true;
             continue;
         }

@@ -222,6 +222,61 @@ def trace(args):
     print("\n".join(lines))
 
 
+def occupancy(args):
+    """Registers, scratch, LDS and the compiler's occupancy (waves per SIMD,
+    from the launch bounds, registers and LDS) of every kernel, from the
+    device compile's kernel-resource-usage remarks."""
+    import subprocess
+    import tempfile
+
+    root = os.path.dirname(HERE)
+    rows = []
+    for src in ("aceapex.hip", "tans.hip"):
+        with tempfile.TemporaryDirectory() as tmp:
+            cmd = [os.environ.get("HIPCC", "/opt/rocm/bin/hipcc"), "--offload-arch=gfx950", "-O3", "-std=c++17",
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I" + os.path.join(root, "include"),
+                   "--offload-device-only", "-c", "-Rpass-analysis=kernel-resource-usage",
+                   os.path.join(HERE, "csrc", src), "-o", os.path.join(tmp, "dev.o")]
+            r = subprocess.run(cmd, capture_output=True, text=True, check=True)
+        cur = None
+        for line in r.stderr.splitlines():
+            m = re.search(r"remark: (?:\S+: )?([A-Za-z ]+(?:\[[^]]+\])?): (\S+) \[-Rpass", line)
+            if not m:
+                continue
+            key, val = m.group(1).strip(), m.group(2)
+            if key == "Function Name":
+                cur = {"kernel": _demangle(val), "source": src}
+                rows.append(cur)
+            elif cur is not None:
+                cur[key] = val
+    lines = ["# Kernel resources and occupancy (gfx950)", "",
+             "From the device compile's resource remarks; occupancy is the compiler's waves per SIMD",
+             "(of 8) allowed by the launch bounds, registers and LDS of one workgroup.", "",
+             "Command (from the repository root):", "", "```",
+             "python -m paper_2606_04268_amd.profiling occupancy --out profiles/occupancy_kernels.md", "```", "",
+             "| Kernel | Source | VGPRs | SGPRs | Scratch (B/lane) | LDS (B/workgroup) | Occupancy (waves/SIMD) |",
+             "|---|---|---|---|---|---|---|"]
+    for c in rows:
+        if c["kernel"].startswith("__"):
+            continue
+        lines.append(f"| {c['kernel']} | {c['source']} | {c.get('VGPRs', '?')} | {c.get('TotalSGPRs', '?')} | "
+                     f"{c.get('ScratchSize [bytes/lane]', '?')} | {c.get('LDS Size [bytes/block]', '?')} | "
+                     f"{c.get('Occupancy [waves/SIMD]', '?')} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _demangle(name: str) -> str:
+    import subprocess
+
+    try:
+        out = subprocess.run(["c++filt", name], capture_output=True, text=True, check=True).stdout.strip()
+    except (OSError, subprocess.CalledProcessError):
+        return name
+    return out.replace("(anonymous namespace)::", "")
+
+
 def load_traffic(path: str):
     """The traffic record of a summary, or None when it is absent or was
     measured on another version of the kernel source."""
@@ -250,6 +305,8 @@ def main():
     s.add_argument("--key", required=True)
     s.add_argument("--command", action="append", default=[])
     s.add_argument("--out", required=True)
+    o = sub.add_parser("occupancy")
+    o.add_argument("--out", required=True)
     t = sub.add_parser("trace")
     t.add_argument("--dir", required=True)
     t.add_argument("--title", required=True)
@@ -261,6 +318,8 @@ def main():
         copycal()
     elif args.cmd == "trace":
         trace(args)
+    elif args.cmd == "occupancy":
+        occupancy(args)
     else:
         summarize(args)
 
