@@ -176,10 +176,11 @@ def measure_plain(name, args, with_plan=True, x=None):
     groups = _abi.timing_read()
     _abi.timing(False)
     ax.check_status(status)
-    exact = bool(torch.equal(out, x_dev))
+    mism, first = ax.compare(out, x_dev, stream=stream)  # k_cmp on the device, outside the timing
+    exact = mism == 0
     host_hash = ax.content_hash(out.cpu().numpy())
     hash_ok = host_hash == ds.info.content_hash
-    assert exact and hash_ok, f"{name}: decode is not bit-exact"
+    assert exact and hash_ok, f"{name}: decode is not bit-exact ({mism} bytes differ, first at {first})"
 
     C, N, M = st["comp_bytes"], st["decoded_bytes"], st["match_bytes"]
     roof = HBM_PEAK_GBPS * N / (C + N + M)
@@ -196,7 +197,8 @@ def measure_plain(name, args, with_plan=True, x=None):
         "decoded_bytes": N, "stream_bytes": C, "ratio": round(N / C, 4) if C else None, "blocks": st["n_blocks"],
         "matches": st["n_seq"], "deep_matches": st["n_deep"], "max_level": st["max_level"], "match_bytes": M,
         "literal_bytes": st["literal_bytes"], "chunks": st["n_chunks"], "encode_s": round(enc_s, 1),
-        "bit_exact": {"device_compare": exact, "xxh3_64": f"{host_hash:016x}", "xxh3_matches_header": hash_ok},
+        "bit_exact": {"device_compare": exact, "k_cmp_mismatches": mism, "xxh3_64": f"{host_hash:016x}",
+                      "xxh3_matches_header": hash_ok},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg[dom], "ms_per_launch": round(dom_ms, 5),
@@ -447,8 +449,9 @@ def measure_batched(args):
         torch.cuda.synchronize()
         ax.check_status(statuses)
         for j in range(len(dss)):
-            if not torch.equal(outs[j][:sizes[j]], origs[j]):
-                raise AssertionError(f"{label}: stream {j} differs from its original")
+            mism, first = ax.compare(outs[j][:sizes[j]], origs[j], stream=stream)
+            if mism:
+                raise AssertionError(f"{label}: stream {j} differs from its original ({mism} bytes, first at {first})")
 
     plan_box = {}
 

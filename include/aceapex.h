@@ -125,8 +125,8 @@ typedef struct {
  * count and size, and the deepest dependency level (Sec. 7.1) that sets the
  * number of wavefronts.  h_len must be >= 64.  Pure host code.  Returns
  * ACEAPEX_OK, ACEAPEX_E_INVAL (null pointer or h_len < 64) or
- * ACEAPEX_E_FORMAT (bad magic or version, unknown flags, levels absent, or
- * fields that contradict each other). */
+ * ACEAPEX_E_FORMAT (bad magic or version, unknown flags, or fields that
+ * contradict each other). */
 int aceapex_probe(const void *h_stream_prefix, size_t h_len, aceapex_info *info);
 
 /* Copy the stream's level table (the number of matches at each dependency
@@ -141,8 +141,10 @@ int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *cou
  * descriptors (n = 1 for aceapex_decode): per chunk a 64-byte descriptor of
  * its slices of the Sec. 3.2 streams, per level of Sec. 7.1 three slot
  * counters, and 12 bytes per match for the level-grouped match records; for
- * a stream without levels, the workspace of aceapex_decode_derive.  Pure
- * host code; returns 0 when a descriptor's info is inconsistent. */
+ * a stream without levels, the workspace of aceapex_decode_derive; with
+ * ACEAPEX_VALIDATE_LEVELS set, a stream with levels needs the larger of its
+ * own and the derive workspace.  Pure host code; returns 0 when a
+ * descriptor's info is inconsistent. */
 size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n);
 
 /* Decode one stream into d_out (Sec. 3.2, Sec. 7.1).  d_workspace must hold
@@ -151,7 +153,16 @@ size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n);
  * the workspace).  Asynchronous on hip_stream.  A host level table
  * (stream->h_levels) whose counts do not add up to n_seq is refused with
  * ACEAPEX_E_FORMAT; one that differs from the stream's own level table makes
- * the device status ACEAPEX_E_CORRUPT. */
+ * the device status ACEAPEX_E_CORRUPT.
+ *
+ * The level launches trust the stored levels for their order.  With the
+ * environment variable ACEAPEX_VALIDATE_LEVELS set (to anything but "" or
+ * "0", read at each call), this call first checks them on the device: every
+ * match's level must exceed the level of each match that writes one of its
+ * source bytes (Sec. 7.1); a stream that breaks this gets ACEAPEX_E_CORRUPT.
+ * The check costs a derive-mode parse and one pass over the matches, and the
+ * larger workspace stated above.  aceapex_decode_many, plans and
+ * aceapex_decode_noalloc do not check. */
 int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capacity,
                    void *d_workspace, size_t ws_bytes, int32_t *d_status, void *hip_stream);
 
@@ -316,6 +327,17 @@ int aceapex_plan_tune(aceapex_plan *plan, void *hip_stream, uint32_t reps, aceap
 
 /* Free the plan (NULL is ignored).  Call it once no launch is in flight. */
 void aceapex_plan_destroy(aceapex_plan *plan);
+
+/* ------------------------------------------------------------ verification */
+
+/* Compare two device buffers of n bytes on the GPU (the decode must give back
+ * its input byte for byte, Sec. 4.3): d_result[0] receives the number of
+ * differing bytes and d_result[1] the index of the first one (n when none).
+ * d_result is a device pointer to two u64, 8-byte aligned, written by the
+ * call's own kernels (no memset).  Asynchronous on hip_stream; read d_result
+ * after synchronizing.  Returns ACEAPEX_OK, ACEAPEX_E_INVAL (null pointers,
+ * misaligned result) or ACEAPEX_E_HIP. */
+int aceapex_compare(const void *d_a, const void *d_b, uint64_t n, uint64_t *d_result, void *hip_stream);
 
 /* ---------------------------------------------- entropy stage (literals) */
 

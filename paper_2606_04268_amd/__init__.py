@@ -228,6 +228,25 @@ def tans_decode(container, out=None, workspace=None, status=None, stream=None, d
     return out, status
 
 
+def compare(a, b, stream=None):
+    """Byte compare of two device tensors on the GPU (aceapex_compare):
+    returns (differing bytes, index of the first; n when none).  Synchronizes
+    the stream to read the result."""
+    torch = _torch()
+    if a.numel() != b.numel() or a.dtype != torch.uint8 or b.dtype != torch.uint8:
+        raise ValueError("compare takes two uint8 tensors of one size")
+    a = a.contiguous()
+    b = b.contiguous()
+    res = torch.empty(2, dtype=torch.int64, device=a.device)
+    _used_on(stream, [res])
+    rc = _abi.compare(a.data_ptr(), b.data_ptr(), a.numel(), res.data_ptr(), _stream_handle(stream))
+    if rc:
+        raise AceapexError(rc, "compare")
+    (stream if stream is not None else torch.cuda.current_stream(a.device)).synchronize()
+    mism, first = (int(v) for v in res.cpu())
+    return mism, first
+
+
 def check_status(status) -> None:
     """Raise if any device status word is nonzero (synchronises)."""
     vals = status.cpu().numpy().ravel()

@@ -74,6 +74,7 @@ class AceapexError(RuntimeError):
 EXPORTS = ("aceapex_probe", "aceapex_level_table", "aceapex_workspace_bytes", "aceapex_decode", "aceapex_decode_many",
            "aceapex_decode_noalloc", "aceapex_decode_host", "aceapex_decode_derive", "aceapex_workspace_bytes_derive",
            "aceapex_tans_probe", "aceapex_tans_workspace_bytes", "aceapex_tans_decode", "aceapex_tans_encode",
+           "aceapex_compare",
            "aceapex_strerror", "aceapex_last_hip_error", "aceapex_enc_defaults", "aceapex_encode",
            "aceapex_free", "aceapex_timing", "aceapex_timing_read", "aceapex_tuning_defaults",
            "aceapex_plan_create", "aceapex_plan_launch", "aceapex_plan_launch_graph", "aceapex_plan_set_tuning",
@@ -115,6 +116,8 @@ def load():
     lib.aceapex_tans_probe.restype = ctypes.c_int
     lib.aceapex_tans_workspace_bytes.argtypes = [ctypes.POINTER(TansInfo)]
     lib.aceapex_tans_workspace_bytes.restype = ctypes.c_size_t
+    lib.aceapex_compare.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
+    lib.aceapex_compare.restype = ctypes.c_int
     lib.aceapex_tans_decode.argtypes = [vp, ctypes.POINTER(TansInfo), vp, ctypes.c_uint64, vp, ctypes.c_size_t, vp, vp]
     lib.aceapex_tans_decode.restype = ctypes.c_int
     lib.aceapex_tans_encode.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(vp)]
@@ -323,6 +326,10 @@ def tans_probe(container) -> TansInfo:
     if rc:
         raise AceapexError(rc, "tans_probe")
     return info
+
+
+def compare(d_a: int, d_b: int, n: int, d_result: int, hip_stream: int) -> int:
+    return load().aceapex_compare(d_a, d_b, n, d_result, hip_stream)
 
 
 def tans_workspace_bytes(info: TansInfo) -> int:

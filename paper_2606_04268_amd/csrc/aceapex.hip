@@ -113,6 +113,7 @@ struct Job {
     uint32_t lv0;        // first entry of the stream in the per-(stream, level) arrays
     uint32_t table;      // 1: the stream stores lvl[] and a level table; 0: the four streams of Sec. 3.2 only
     uint32_t derive;     // 1: levels derived on the device (records in stream order, single stream only)
+    uint32_t validate;   // 1: the stored levels are being checked (derive pass), or were (decode keeps the verdict)
 };
 
 // A decode: one stream (jobs == nullptr) or a batch of streams.
@@ -554,8 +555,10 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
             sig += mixed;
         }
         // every match counted exactly once, and the levels the host scheduled are these
-        if (t == 0)
-            *j.status = (carry != j.n_seq || (B.has_sig && sig != B.level_sig)) ? ACEAPEX_E_CORRUPT : 0;
+        if (t == 0) {
+            const int32_t before = j.validate ? *j.status : 0;  // the verdict of the level check, if one ran
+            *j.status = (carry != j.n_seq || (B.has_sig && sig != B.level_sig)) ? ACEAPEX_E_CORRUPT : before;
+        }
     }
     if (B.jobs && blockIdx.x < B.n_jobs) {
         // batch: this stream's level cursors (slots were laid out on the host
@@ -992,7 +995,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
             }
             uint32_t *rr = B.recs + 3ull * i;
             rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u];
-            B.dlevel[i] = NONE;
+            B.dlevel[i] = j.validate ? l[u] : NONE;  // the stored level, when it is being checked
             B.dhead[i] = NONE;
             B.dcur[i] = src[u];
             B.dmax[i] = 0;
@@ -1379,6 +1382,31 @@ __global__ void __launch_bounds__(NT_TAIL) k_derive_tail(Batch B, uint32_t k0)
 }
 
 // Every match must have run (a stream whose sources form no valid order fails).
+// Check of stored levels (Sec. 7.1), on the records in stream order with
+// their stored levels (a derive-mode parse with validate set): every writer
+// of a match's source bytes must have a lower level than the match, or the
+// level launches would run the match before its source is final.  A stream
+// that breaks this fails the decode; literal bytes have no writer.
+__global__ void __launch_bounds__(NT) k_validate(Batch B)
+{
+    const uint32_t M = B.n_seq, N = B.one.n;
+    if (*B.one.status) return;  // already failed (corrupt sections): the records may be incomplete
+    for (uint32_t m = blockIdx.x * NT + threadIdx.x; m < M; m += gridDim.x * NT) {
+        const uint32_t *r = B.recs + 3ull * m;
+        const uint32_t dst = r[0], src = r[1], len = r[2], lv = B.dlevel[m];
+        if ((uint64_t)src + len > dst || (uint64_t)dst + len > N) continue;  // rejected by the parse
+        for (uint32_t b = src; b < src + len;) {
+            uint32_t run_end;
+            const uint32_t w = writer_of(B, b, M, N, run_end);
+            if (w != NONE && B.dlevel[w] >= lv) {
+                fail(B.one, ACEAPEX_E_CORRUPT);
+                break;
+            }
+            b = min(src + len, max(run_end, b + 1));
+        }
+    }
+}
+
 __global__ void k_derive_final(Batch B)
 {
     if (threadIdx.x == 0 && *B.one.status == 0 && B.dcnt[DC_DONE] != B.n_seq) fail(B.one, ACEAPEX_E_CORRUPT);
@@ -1646,20 +1674,33 @@ WsDerive ws_derive(const aceapex_info &in)
     return w;
 }
 
-// The workspace of the stream's own decode: stored levels or derived ones.
-size_t ws_one(const aceapex_info &in) { return has_table(in) ? ws_single(in).total : ws_derive(in).total; }
+// ACEAPEX_VALIDATE_LEVELS set to anything but "" or "0": aceapex_decode
+// checks a stream's stored levels before it trusts them.
+bool validate_levels()
+{
+    const char *v = getenv("ACEAPEX_VALIDATE_LEVELS");
+    return v && v[0] && strcmp(v, "0") != 0;
+}
+
+// The workspace of the stream's own decode: stored levels (and their check,
+// when asked for) or derived ones.
+size_t ws_one(const aceapex_info &in)
+{
+    if (!has_table(in)) return ws_derive(in).total;
+    return validate_levels() ? std::max(ws_single(in).total, ws_derive(in).total) : ws_single(in).total;
+}
 
 // Decode one stream deriving its levels on the device (see the level
 // derivation kernels); d_levels, when not null, receives each match's level
 // in stream order.  The host reads the queue length back every few levels
 // (the number of levels is found on the device), so this call returns once
 // the last level has been enqueued.
-int launch_derive(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, uint32_t *d_levels,
-                  hipStream_t st)
+// The kernel arguments of a derive-mode decode (records in stream order).
+void derive_batch(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, uint32_t *d_levels,
+                  Batch &B)
 {
     const aceapex_info &in = s.info;
     const WsDerive w = ws_derive(in);
-    Batch B;
     memset(&B, 0, sizeof B);
     B.one = make_job(s, d_out, d_status ? d_status : (int32_t *)(ws + w.status), (ChunkDesc *)(ws + w.chunks),
                      ws + w.blk_ok, 0, 0, 0);
@@ -1682,7 +1723,12 @@ int launch_derive(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     B.n_seq = in.n_seq;
     B.long_copy = LONG_COPY;
     B.xcd_parts = XCD_PARTS;
-    const uint32_t M = in.n_seq;
+}
+
+// Setup, derive-mode parse (literals placed, records in stream order) and
+// the page index.
+void enqueue_derive_parse(const Batch &B, hipStream_t st)
+{
     {
         PhaseScope ps(PH_SETUP, st);
         hipLaunchKernelGGL(k_setup, dim3(std::max<uint32_t>(1, std::min<uint32_t>(B.n_blocks, 65535))), dim3(NT), 0,
@@ -1691,8 +1737,18 @@ int launch_derive(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     if (B.n_blocks) {
         PhaseScope ps(PH_PARSE, st);
         launch_parse<false>(B, B.n_chunks, st);
-        if (M) hipLaunchKernelGGL(k_pages, dim3(std::min<uint32_t>(DERIVE_WG_MAX, M / NT + 1)), dim3(NT), 0, st, B);
+        if (B.n_seq)
+            hipLaunchKernelGGL(k_pages, dim3(std::min<uint32_t>(DERIVE_WG_MAX, B.n_seq / NT + 1)), dim3(NT), 0, st, B);
     }
+}
+
+int launch_derive(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, uint32_t *d_levels,
+                  hipStream_t st)
+{
+    Batch B;
+    derive_batch(s, d_out, ws, d_status, d_levels, B);
+    const uint32_t M = B.n_seq;
+    enqueue_derive_parse(B, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e);
     if (!M) return ACEAPEX_OK;
@@ -1716,6 +1772,24 @@ int launch_derive(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     }
     hipLaunchKernelGGL(k_derive_final, dim3(1), dim3(64), 0, st, B);
     e = hipGetLastError();
+    return e == hipSuccess ? ACEAPEX_OK : hip_fail(e);
+}
+
+// The check of a stream's stored levels that ACEAPEX_VALIDATE_LEVELS asks
+// for: a derive-mode parse that keeps the stored levels, the page index,
+// then k_validate.  It leaves its verdict in the status word, which the
+// decode that follows keeps.
+int launch_validate(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st)
+{
+    Batch B;
+    derive_batch(s, d_out, ws, d_status, nullptr, B);
+    B.one.validate = 1;
+    enqueue_derive_parse(B, st);
+    if (B.n_seq) {
+        PhaseScope ps(PH_PARSE, st);
+        hipLaunchKernelGGL(k_validate, dim3(std::min<uint32_t>(DERIVE_WG_MAX, B.n_seq / NT + 1)), dim3(NT), 0, st, B);
+    }
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? ACEAPEX_OK : hip_fail(e);
 }
 
@@ -1899,10 +1973,12 @@ void enqueue_group(const Group &g, const Tune &tn, hipStream_t st, bool timed)
     }
 }
 
-int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st)
+int launch_single(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_status, hipStream_t st,
+                  bool keep_verdict = false)
 {
     Group g;
     build_single(s, d_out, ws, d_status, g);
+    g.B.one.validate = keep_verdict ? 1u : 0u;
     enqueue_group(g, Tune(), st, true);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e);
@@ -2090,7 +2166,10 @@ int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capac
     if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need) return ACEAPEX_E_WORKSPACE;
     if (!has_table(stream->info))  // no stored levels: derived on the device
         return launch_derive(*stream, d_out, (uint8_t *)d_workspace, d_status, nullptr, (hipStream_t)hip_stream);
-    return launch_single(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream);
+    const bool check = validate_levels();
+    if (check && (rc = launch_validate(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream)))
+        return rc;
+    return launch_single(*stream, d_out, (uint8_t *)d_workspace, d_status, (hipStream_t)hip_stream, check);
 }
 
 int aceapex_decode_derive(const aceapex_stream *stream, void *d_out, uint64_t out_capacity, void *d_workspace,

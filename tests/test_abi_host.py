@@ -140,3 +140,18 @@ def test_plan_argument_errors_need_no_gpu():
     assert lib.aceapex_plan_set_tuning(None, ctypes.byref(t)) == _abi.E_INVAL
     assert lib.aceapex_plan_tune(None, None, 1, None) == _abi.E_INVAL
     lib.aceapex_plan_destroy(None)
+
+
+def test_workspace_follows_level_validation(monkeypatch):
+    """With ACEAPEX_VALIDATE_LEVELS set, a stream with levels needs room for
+    the derive-mode check as well as its decode; "0" leaves it off."""
+    x = synth.markov(1 << 20, 5)
+    info = _abi.probe(oracle.encode(x, block_log2=16))
+    desc = [_abi.Desc(_abi.Stream(0, info, None), 0, info.decoded_bytes, 0)]
+    monkeypatch.delenv("ACEAPEX_VALIDATE_LEVELS", raising=False)
+    plain = _abi.workspace_bytes(desc)
+    monkeypatch.setenv("ACEAPEX_VALIDATE_LEVELS", "0")
+    assert _abi.workspace_bytes(desc) == plain
+    monkeypatch.setenv("ACEAPEX_VALIDATE_LEVELS", "1")
+    checked = _abi.workspace_bytes(desc)
+    assert checked == max(plain, _abi.workspace_bytes_derive(info)) and checked > plain
