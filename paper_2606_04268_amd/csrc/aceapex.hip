@@ -80,6 +80,7 @@ constexpr uint32_t XCD_PARTS = 8;           // contiguous parts of a level's rec
 constexpr uint32_t TILE_BYTES = 16384;      // output span of a chunk assembled in LDS by k_parse
 constexpr uint64_t CHUNKS_MAX = 1ull << 24;  // chunks of one launch sequence (the k_parse grid), at most
 constexpr uint32_t COOP_RUNS = 8;          // k_parse: longer literal runs of a wave slot placed by the whole wave
+constexpr uint32_t LEVEL_WG1 = 64;          // k_level with one record per thread: workgroup size (one wave)
 
 typedef uint16_t u16u __attribute__((aligned(1)));
 typedef uint32_t u32u __attribute__((aligned(1)));
@@ -140,6 +141,21 @@ struct Batch {
     uint32_t *dready;           // matches found ready at this level
     uint32_t *dpage;            // per 256 output bytes: first match whose dst is at or past it
     uint32_t *dcnt;             // counters (DC_*)
+};
+
+// The arguments of a level launch: what k_level reads of a Batch, under the
+// same member names, so that its launch carries a small kernel-argument
+// block (a launch per level; measured faster than passing the whole Batch).
+struct LevelArgs {
+    struct {
+        uint8_t *out;
+        int32_t *status;
+        uint32_t n, max_level;
+    } one;                      // the stream of a single-stream decode
+    const Job *jobs;            // batched: the stream table, or nullptr
+    uint32_t *recs;
+    const uint32_t *rec_lo, *rec_hi, *cursor, *level_lo;
+    uint32_t n_jobs, long_copy, xcd_parts;
 };
 
 constexpr uint32_t NONE = 0xffffffffu;
@@ -295,7 +311,8 @@ __device__ __forceinline__ void run_records(uint8_t *const *ob, const uint32_t *
 // Slots [lo, hi) of level k: in a single-stream decode the filled part of the
 // level; in a batch the level's slots over all streams (unfilled slots are
 // rejected record by record).
-__device__ __forceinline__ void level_range(const Batch &B, uint32_t k, uint32_t &lo, uint32_t &hi)
+template <class A>
+__device__ __forceinline__ void level_range(const A &B, uint32_t k, uint32_t &lo, uint32_t &hi)
 {
     if (B.jobs) {
         lo = B.level_lo[k];
@@ -308,8 +325,8 @@ __device__ __forceinline__ void level_range(const Batch &B, uint32_t k, uint32_t
 
 // Raw words of the records r0 + u*stride (u < R), without waiting
 // between them; a slot at or past r_end gets lj = 0 (no match).
-template <uint32_t R>
-__device__ __forceinline__ void fetch_records(const Batch &B, uint32_t r0, uint32_t stride, uint32_t r_end,
+template <uint32_t R, class A>
+__device__ __forceinline__ void fetch_records(const A &B, uint32_t r0, uint32_t stride, uint32_t r_end,
                                               uint32_t *dst, uint32_t *src, uint32_t *lj)
 {
 #pragma unroll
@@ -326,8 +343,8 @@ __device__ __forceinline__ void fetch_records(const Batch &B, uint32_t r0, uint3
 // The stream of each fetched record: its output, size and status.  In a
 // batch every slot of a level was filled in this decode or given length 0 by
 // k_seal, so the stream index carried by the record is all that is needed.
-template <bool BATCH, uint32_t R>
-__device__ __forceinline__ void resolve_records(const Batch &B, const uint32_t *lj, uint8_t **ob, uint32_t *on,
+template <bool BATCH, uint32_t R, class A>
+__device__ __forceinline__ void resolve_records(const A &B, const uint32_t *lj, uint8_t **ob, uint32_t *on,
                                                 int32_t **sp, uint32_t *len)
 {
 #pragma unroll
@@ -354,8 +371,8 @@ __device__ __forceinline__ void resolve_records(const Batch &B, const uint32_t *
 }
 
 // Fetch and resolve R records (see fetch_records, resolve_records).
-template <bool BATCH, uint32_t R>
-__device__ __forceinline__ void load_records(const Batch &B, uint32_t r0, uint32_t stride,
+template <bool BATCH, uint32_t R, class A>
+__device__ __forceinline__ void load_records(const A &B, uint32_t r0, uint32_t stride,
                                              uint32_t r_end, uint8_t **ob, uint32_t *on, int32_t **sp,
                                              uint32_t *dst, uint32_t *src, uint32_t *len)
 {
@@ -1096,8 +1113,9 @@ __global__ void __launch_bounds__(NT) k_seal(Batch B)
 // --------------------------------------------------------------- k_level
 
 // One level: each thread takes R records per round (R = 1 while the level
-// fits the launch at one record per thread, so that a mid-size level is
-// spread over as many workgroups as it can use; R = 2 for larger levels).
+// fits the launch at one record per thread, in workgroups of one wave, so
+// that a mid-size level is spread over every CU it can use; R = 2, in
+// workgroups of NT threads, for larger levels).
 // The level's slots are split into one contiguous part per XCD; the
 // workgroups of an XCD sweep its part together, tile after tile, so that the
 // destinations and sources they touch at one time share its L2.  Workgroup i
@@ -1112,24 +1130,25 @@ __global__ void __launch_bounds__(NT) k_seal(Batch B)
 // only a corrupt stream can do; such a slot's stale record is still bounds-
 // checked like any other.
 template <bool BATCH, uint32_t R>
-__global__ void __launch_bounds__(NT) k_level(Batch B, uint32_t k, uint32_t lo, uint32_t hi, uint32_t check)
+__global__ void __launch_bounds__(NT) k_level(LevelArgs B, uint32_t k, uint32_t lo, uint32_t hi, uint32_t check)
 {
     uint32_t R0 = lo, R1 = hi;
     if (lo == NO_RANGE) level_range(B, k, R0, R1);
     if (!BATCH && check && blockIdx.x == 0) {
-        for (uint32_t i = threadIdx.x; i <= B.one.max_level; i += NT)
-            if (B.cursor[i] != B.rec_hi[i]) fail(B.one, ACEAPEX_E_CORRUPT);
+        for (uint32_t i = threadIdx.x; i <= B.one.max_level; i += blockDim.x)
+            if (B.cursor[i] != B.rec_hi[i]) atomicCAS(B.one.status, 0, ACEAPEX_E_CORRUPT);
     }
     const uint32_t G = gridDim.x, P = G < B.xcd_parts ? G : B.xcd_parts;
     const uint32_t x = blockIdx.x % P, w = blockIdx.x / P, W = (G - x + P - 1) / P;
     const uint64_t S = R1 > R0 ? R1 - R0 : 0;
     const uint32_t p0 = R0 + (uint32_t)(S * x / P), p1 = R0 + (uint32_t)(S * (x + 1) / P);
-    for (uint32_t r0 = p0 + w * (NT * R) + threadIdx.x;; r0 += W * (NT * R)) {
+    const uint32_t BS = blockDim.x;
+    for (uint32_t r0 = p0 + w * (BS * R) + threadIdx.x;; r0 += W * (BS * R)) {
         if (__ballot(r0 < p1) == 0) break;
         uint8_t *ob[R];
         int32_t *sp[R];
         uint32_t on[R], dst[R], src[R], len[R];
-        load_records<BATCH, R>(B, min(r0, p1 - 1), NT, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
+        load_records<BATCH, R>(B, min(r0, p1 - 1), BS, r0 < p1 ? p1 : 0, ob, on, sp, dst, src, len);
         run_records<R>(ob, on, sp, dst, src, len, B.long_copy);
     }
 }
@@ -1503,10 +1522,25 @@ template <bool BATCH>
 void launch_level(const Batch &B, uint32_t k, uint64_t cnt, uint32_t lo, uint32_t hi, uint32_t check, const Tune &tn,
                   hipStream_t st)
 {
-    if (cnt <= (uint64_t)tn.level_wg_max * NT)
-        hipLaunchKernelGGL((k_level<BATCH, 1>), dim3(level_wgs(cnt, 1, tn)), dim3(NT), 0, st, B, k, lo, hi, check);
+    LevelArgs a;
+    a.one.out = B.one.out;
+    a.one.status = B.one.status;
+    a.one.n = B.one.n;
+    a.one.max_level = B.one.max_level;
+    a.jobs = B.jobs;
+    a.recs = B.recs;
+    a.rec_lo = B.rec_lo;
+    a.rec_hi = B.rec_hi;
+    a.cursor = B.cursor;
+    a.level_lo = B.level_lo;
+    a.n_jobs = B.n_jobs;
+    a.long_copy = B.long_copy;
+    a.xcd_parts = B.xcd_parts;
+    if (cnt <= (uint64_t)tn.level_wg_max * NT)  // one record per thread, in workgroups of one wave
+        hipLaunchKernelGGL((k_level<BATCH, 1>), dim3((uint32_t)std::max<uint64_t>(1, (cnt + LEVEL_WG1 - 1) / LEVEL_WG1)),
+                           dim3(LEVEL_WG1), 0, st, a, k, lo, hi, check);
     else
-        hipLaunchKernelGGL((k_level<BATCH, ROUND_LEVEL>), dim3(level_wgs(cnt, ROUND_LEVEL, tn)), dim3(NT), 0, st, B, k,
+        hipLaunchKernelGGL((k_level<BATCH, ROUND_LEVEL>), dim3(level_wgs(cnt, ROUND_LEVEL, tn)), dim3(NT), 0, st, a, k,
                            lo, hi, check);
 }
 
