@@ -40,7 +40,7 @@ namespace {
 constexpr uint32_t TH = 32, TC = 512;     // header and counts bytes
 constexpr uint32_t R_MIN = 8, R_MAX = 12;  // table sizes 256 .. 4096 entries
 constexpr int NTT = 256;                   // threads of the lane decoder
-constexpr int NTB = 1024;                  // threads of the table build (four per symbol)
+constexpr int NTB = 256;                   // threads per workgroup of the table build (one per symbol and entry)
 
 
 __host__ __device__ inline uint32_t rd32(const uint8_t *p)
@@ -59,61 +59,68 @@ struct TansArgs {
     uint32_t n, R, lanes, bs_bytes;
 };
 
-// One workgroup of NTB threads: the decode table from the counts.  Symbol
-// ranges come from a scan of the counts and the spread from a binary search
-// per table entry.  State values are then dealt in position order without a
-// serial pass: thread (q, s) counts symbol s in quarter q of the positions,
-// the counts of the quarters before q give the state value its first
-// occurrence in quarter q takes, and a second pass writes the quarter's
-// entries of s in increasing position order.
+// sum_{i<n} floor((a*i + b) / m) for m >= 1 and a, b >= 0, by the Euclidean
+// reduction of floor sums (O(log m) steps).  In 32 bits: for tables of at
+// most 2^12 entries every term here stays below 2^26.
+__device__ __forceinline__ uint32_t floor_sum(uint32_t n, uint32_t m, uint32_t a, uint32_t b)
+{
+    uint32_t ans = 0;
+    for (;;) {
+        if (a >= m) {
+            ans += (n - 1) * n / 2 * (a / m);
+            a %= m;
+        }
+        if (b >= m) {
+            ans += n * (b / m);
+            b %= m;
+        }
+        const uint32_t y = a * n + b;
+        if (y < m) return ans;
+        n = y / m;
+        b = y % m;
+        const uint32_t t = m;
+        m = a;
+        a = t;
+    }
+}
+
+// The decode table from the counts, one thread per table entry in L / 256
+// workgroups that each scan the counts.  Each table entry i in symbol order
+// finds its symbol s
+// by binary search and its position p = (i * step) mod L.  Its state value
+// is c_s plus the number of s's entries whose positions lie below p; entry j
+// of s sits at (j * step) mod L, and [x mod L < p] = 1 + floor(x / L) -
+// floor((x + L - p) / L), so that number is c_s plus a difference of two
+// floor sums over s's range of entries, with no pass over the table.
 __global__ void __launch_bounds__(NTB) k_tans_table(TansArgs A)
 {
-    __shared__ uint32_t cnt[256], cum[257], inq[4][256];
-    __shared__ uint32_t symw[(1u << R_MAX) / 4];  // the spread, four symbols per word
+    __shared__ uint32_t cum[257];
     const uint32_t t = threadIdx.x, L = 1u << A.R, step = (L >> 1) + (L >> 3) + 3;
-    if (t < 256) {
-        cnt[t] = A.in[TH + 2 * t] | ((uint32_t)A.in[TH + 2 * t + 1] << 8);
-        cum[t + 1] = cnt[t];
-    }
+    cum[t + 1] = A.in[TH + 2 * t] | ((uint32_t)A.in[TH + 2 * t + 1] << 8);
     if (t == 0) cum[0] = 0;
     __syncthreads();
     for (uint32_t d = 1; d < 256; d <<= 1) {  // inclusive scan of cum[1..256]
-        const uint32_t v = (t < 256 && t >= d) ? cum[t + 1 - d] : 0;
+        const uint32_t v = t >= d ? cum[t + 1 - d] : 0;
         __syncthreads();
-        if (t < 256) cum[t + 1] += v;
+        cum[t + 1] += v;
         __syncthreads();
     }
-    if (t == 0) *A.status = (A.n && cum[256] != L) ? ACEAPEX_E_CORRUPT : 0;  // the decode's status starts here
+    if (blockIdx.x == 0 && t == 0)
+        *A.status = (A.n && cum[256] != L) ? ACEAPEX_E_CORRUPT : 0;  // the decode's status starts here
     if (cum[256] != L) return;
-    uint8_t *sym = (uint8_t *)symw;
-    for (uint32_t i = t; i < L; i += NTB) {
+    {
+        const uint32_t i = blockIdx.x * NTB + t;  // < L: the grid is L / NTB workgroups
         uint32_t lo = 0, hi = 255;  // the symbol whose cumulative range holds i
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
             if (cum[mid] <= i) lo = mid; else hi = mid - 1;
         }
-        sym[(uint32_t)(((uint64_t)i * step) & (L - 1))] = (uint8_t)lo;
-    }
-    __syncthreads();
-    const uint32_t s = t & 255, q = t >> 8, W = L / 16;  // words per quarter
-    uint32_t c = 0;
-    for (uint32_t w = q * W; w < (q + 1) * W; w++) {
-        const uint32_t x = symw[w] ^ (s * 0x01010101u);  // zero bytes where the symbol is s
-        c += ((x & 0xffu) == 0) + ((x & 0xff00u) == 0) + ((x & 0xff0000u) == 0) + ((x >> 24) == 0);
-    }
-    inq[q][s] = c;
-    __syncthreads();
-    uint32_t y = cnt[s];
-    for (uint32_t k = 0; k < q; k++) y += inq[k][s];
-    for (uint32_t w = q * W; w < (q + 1) * W; w++) {
-        const uint32_t x = symw[w] ^ (s * 0x01010101u);
-        if ((x & 0xffu) && (x & 0xff00u) && (x & 0xff0000u) && (x >> 24)) continue;
-        for (uint32_t k = 0; k < 4; k++) {
-            if ((x >> (8 * k)) & 0xffu) continue;
-            const uint32_t nb = A.R - (31 - __clz(y));
-            A.table[4 * w + k] = s | (nb << 8) | ((y << nb) << 13);
-            y++;
-        }
+        const uint32_t c0 = cum[lo], c = cum[lo + 1] - c0, p = (uint32_t)(((uint64_t)i * step) & (L - 1));
+        const uint32_t x0 = step * c0;
+        const uint32_t below = c + floor_sum(c, L, step, x0) - floor_sum(c, L, step, x0 + L - p);
+        const uint32_t y = c + below;
+        const uint32_t nb = A.R - (31 - __clz(y));
+        A.table[p] = lo | (nb << 8) | ((y << nb) << 13);
     }
 }
 
@@ -222,7 +229,7 @@ int aceapex_tans_decode(const void *d_in, const aceapex_tans_info *info, void *d
     A.R = info->table_log;
     A.lanes = info->lanes;
     A.bs_bytes = info->bitstream_bytes;
-    hipLaunchKernelGGL(k_tans_table, dim3(1), dim3(NTB), 0, st, A);
+    hipLaunchKernelGGL(k_tans_table, dim3((1u << info->table_log) / NTB), dim3(NTB), 0, st, A);
     hipLaunchKernelGGL(k_tans, dim3((info->lanes + NTT - 1) / NTT), dim3(NTT), 0, st, A);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
