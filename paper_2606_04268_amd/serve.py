@@ -7,7 +7,8 @@ The loop
   * admits waiting requests first-come first-served while their output and
     workspace fit in the device-memory budget (an arena carved from one
     preallocated buffer; memory returns when a request completes),
-  * launches the admitted requests as one batched decode (aceapex_decode_many)
+  * launches the admitted requests as one batched decode (aceapex_decode_many;
+    streams without stored levels are decoded one by one on the same lane)
     on a free HIP stream, so that up to `lanes` batches run on the GPU at once
     and requests that arrive while others run join the next batch,
   * records, per request, the time from its arrival to the moment the host
@@ -332,9 +333,20 @@ class Server:
             r.admitted = -1.0
             waiting.insert(0, r)
         ws = self.ws[lane]
-        rc = _abi.decode_many(descs, ws.data_ptr(), ws.numel(), stream.cuda_stream)
-        if rc:
-            raise AceapexError(rc, "decode_many")
+        # streams with stored levels go in one batched decode; streams in the
+        # four-section format (levels derived on the device) one at a time,
+        # after it on the same lane and workspace
+        plain = [d for d in descs if d.s.info.flags & 8]
+        if plain:
+            rc = _abi.decode_many(plain, ws.data_ptr(), ws.numel(), stream.cuda_stream)
+            if rc:
+                raise AceapexError(rc, "decode_many")
+        for d in descs:
+            if not d.s.info.flags & 8:
+                rc = _abi.decode(d.s, d.d_out, d.out_capacity, ws.data_ptr(), ws.numel(), d.d_status,
+                                 stream.cuda_stream)
+                if rc:
+                    raise AceapexError(rc, "decode")
         ev = torch.cuda.Event()
         ev.record(stream)
         now = time.perf_counter() - t0

@@ -155,3 +155,13 @@ def test_workspace_follows_level_validation(monkeypatch):
     monkeypatch.setenv("ACEAPEX_VALIDATE_LEVELS", "1")
     checked = _abi.workspace_bytes(desc)
     assert checked == max(plain, _abi.workspace_bytes_derive(info)) and checked > plain
+
+
+def test_compare_argument_errors_need_no_gpu():
+    """aceapex_compare refuses a null or misaligned result pointer and null
+    buffers before it touches the GPU."""
+    lib = _abi.load()
+    assert _abi.compare(0, 0, 16, 0, 0) == _abi.E_INVAL  # no result
+    assert _abi.compare(0x1000, 0x2000, 16, 0x3004, 0) == _abi.E_INVAL  # result not 8-byte aligned
+    assert _abi.compare(0, 0x2000, 16, 0x3000, 0) == _abi.E_INVAL  # null buffer with n > 0
+    assert lib is not None

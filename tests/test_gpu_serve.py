@@ -1,6 +1,7 @@
 """GPU checks of the serving loop: every request served under continuous
 batching decodes exactly as the same stream decoded alone, whatever the mix
-it was batched with and whichever device (GPU, or the host decoder) the
+it was batched with (streams with stored levels and streams in the
+four-section format), whichever device (GPU, or the host decoder) the
 request was routed to, and a tight memory budget only delays admission."""
 import numpy as np
 import pytest
@@ -26,6 +27,15 @@ def pool():
         x = synth.make(["markov", "fastq", "wiki", "random"][i % 4], n, 900 + i)
         s = oracle.encode(x, block_log2=int(rng.choice([16, 20])), flatten=int(i % 3),
                           max_depth=int(rng.choice([0, 4])))
+        originals.append(x)
+        streams.append(ax.to_device(s))
+        hosts.append(s)
+    # streams in the four-section format (no stored levels): their levels
+    # are derived on the device, or they go to the host decoder
+    for kind, seed in (("wiki", 950), ("fastq", 951)):
+        x = synth.make(kind, 600_000, seed)
+        s = oracle.encode(x, block_log2=16, levels=0)
+        assert oracle.header_fields(s)["flags"] & 8 == 0
         originals.append(x)
         streams.append(ax.to_device(s))
         hosts.append(s)
