@@ -198,8 +198,10 @@ size_t aceapex_workspace_bytes_derive(const aceapex_info *info);
  * overflow the 32-bit indexes of one sequence, runs as several consecutive
  * sequences.  Without the tables the streams are decoded one after the other.
  * Returns the first synchronous error; per-stream device errors go to each
- * d_status.  A stream without levels is refused (ACEAPEX_E_UNSUPPORTED): its
- * derivation reads back from the device, one stream per call.  Host level
+ * d_status.  Streams without stored levels (flags bit 3 clear) are decoded
+ * after the others, one by one, with their levels derived on the device as
+ * in aceapex_decode_derive; their derivation reads counters back, so a call
+ * that holds such a stream returns only once it is decoded.  Host level
  * tables are checked as in aceapex_decode: a table
  * whose counts do not add up to n_seq is refused (ACEAPEX_E_FORMAT), one that
  * differs from the stream's own table fails that stream (ACEAPEX_E_CORRUPT). */

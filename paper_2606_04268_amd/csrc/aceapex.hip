@@ -2245,29 +2245,55 @@ int aceapex_decode_many(const aceapex_desc *h_descs, uint32_t n, void *d_workspa
 {
     if (!h_descs && n) return ACEAPEX_E_INVAL;
     bool tables = true;
+    uint32_t n_free = 0;  // streams without stored levels
     for (uint32_t i = 0; i < n; i++) {
         int rc = check_stream_args(&h_descs[i].s, h_descs[i].d_out, h_descs[i].out_capacity);
         if (rc) return rc;
-        if (!has_table(h_descs[i].s.info)) return ACEAPEX_E_UNSUPPORTED;  // derived levels: one stream per call
+        if (!has_table(h_descs[i].s.info)) {
+            n_free++;
+            continue;
+        }
         tables = tables && h_descs[i].s.h_levels;
     }
     if (n && (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < many_bytes(h_descs, n)))
         return ACEAPEX_E_WORKSPACE;
-    uint8_t *ws = (uint8_t *)d_workspace;
     hipStream_t st = (hipStream_t)hip_stream;
-    if (!tables) {  // without the host level tables: one stream after the other
-        for (uint32_t i = 0; i < n; i++) {
-            int rc = launch_single(h_descs[i].s, h_descs[i].d_out, ws, h_descs[i].d_status, st);
-            if (rc) return rc;
-            ws += ws_single(h_descs[i].s.info).total;
+    // the streams with stored levels (all of them, when none lacks levels)
+    std::vector<aceapex_desc> kept;
+    const aceapex_desc *d = h_descs;
+    uint32_t m_levels = n;
+    if (n_free) {
+        try {
+            for (uint32_t i = 0; i < n; i++)
+                if (has_table(h_descs[i].s.info)) kept.push_back(h_descs[i]);
+        } catch (const std::bad_alloc &) {
+            return ACEAPEX_E_NOMEM;
         }
-        return ACEAPEX_OK;
+        d = kept.data();
+        m_levels = (uint32_t)kept.size();
     }
-    for (uint32_t i = 0, m; i < n; i += m) {
-        m = group_size(h_descs + i, n - i);
-        int rc = launch_batch(h_descs + i, m, ws, st);
+    uint8_t *ws = (uint8_t *)d_workspace;
+    if (!tables) {  // without the host level tables: one stream after the other
+        for (uint32_t i = 0; i < m_levels; i++) {
+            int rc = launch_single(d[i].s, d[i].d_out, ws, d[i].d_status, st);
+            if (rc) return rc;
+            ws += ws_single(d[i].s.info).total;
+        }
+    } else {
+        for (uint32_t i = 0, m; i < m_levels; i += m) {
+            m = group_size(d + i, m_levels - i);
+            int rc = launch_batch(d + i, m, ws, st);
+            if (rc) return rc;
+            ws += ws_batch(d + i, m).total;
+        }
+    }
+    // then the streams without levels, one after the other from the start of
+    // the workspace (the launches above come first on the stream): their
+    // derivation reads counters back, so the call returns once they are done
+    for (uint32_t i = 0; i < n && n_free; i++) {
+        if (has_table(h_descs[i].s.info)) continue;
+        int rc = launch_derive(h_descs[i].s, h_descs[i].d_out, (uint8_t *)d_workspace, h_descs[i].d_status, nullptr, st);
         if (rc) return rc;
-        ws += ws_batch(h_descs + i, m).total;
     }
     return ACEAPEX_OK;
 }

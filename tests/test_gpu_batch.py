@@ -177,3 +177,19 @@ def test_decode_on_a_side_stream_without_buffers():
         assert np.array_equal(o[:x.size].cpu().numpy(), x)
         assert np.array_equal(o2[:x.size].cpu().numpy(), x)
     assert (sts.cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("with_tables", [True, False], ids=["batched", "one_by_one"])
+def test_batch_with_streams_without_levels(with_tables):
+    """Streams in the four-section format (no stored levels) inside a batch:
+    they are decoded after the others with their levels derived on the
+    device; every stream matches its original and the oracle's decode."""
+    pairs = mixed_streams(12, 5)
+    for i, kind in enumerate(["wiki", "fastq", "markov", "wiki"]):
+        x = synth.make(kind, 200_000 + 77_777 * i, 60 + i)
+        pairs.insert(3 * i + 1, (x, oracle.encode(x, block_log2=[12, 16, 20, 14][i], levels=0)))
+    say(f"[gpu] decode_many {len(pairs)} streams, 4 without levels, with_tables={with_tables}")
+    res, st = run_batch(pairs, with_tables)
+    assert (st == 0).all(), st
+    for (x, s), got in zip(pairs, res):
+        assert np.array_equal(got, x) and np.array_equal(got, oracle.decode(s))
