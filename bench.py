@@ -54,7 +54,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "decoded GB/s at 1 MI355X (bit-exact) vs HBM peak; served p50/p99 latency"
-HOST_THREADS = 16  # worker threads on the host (the GPU machine's CPU share)
+HOST_THREADS = 16  # worker threads of the host encoder and host decoder
 
 WORKLOADS = {
     "wiki1g": dict(kind="wiki", size=1 << 30, seed=0xACE2, enc=dict(),
