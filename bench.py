@@ -36,6 +36,9 @@ Other modes (one JSON line each):
   --mode batched  the batched entry alone
   --mode served   the served entry with a sweep of offered loads
   --mode entropy  the entropy stage alone on one workload's literals (--workload)
+  --mode derive   one workload (--workload) encoded without stored levels,
+                  decoded with levels derived on the device, beside the same
+                  text with stored levels
   --mode sweep    depth limit D (1, 2, 10, unlimited) x chain flattening (off,
                   R1, R2) on wiki-like text and FASTQ-like data (32 MiB each):
                   ratio, deepest level and decoded GB/s (Sec. 7.4, Table 5)
@@ -715,6 +718,52 @@ def run_entropy(args):
     print(json.dumps(line), flush=True)
 
 
+def run_derive(args):
+    """One workload encoded in the four sections of Sec. 3.2 only (no stored
+    levels), decoded with aceapex_decode, which derives every match's level
+    on the device while the wavefront runs (it reads a counter back every few
+    levels, so a decode includes those host round trips); beside it the same
+    text with stored levels."""
+    import torch
+
+    import synth
+    import paper_2606_04268_amd as ax
+
+    wl = WORKLOADS[args.workload]
+    x = synth.make(wl["kind"], wl["size"], wl["seed"])
+    dev = torch.device("cuda:0")
+    x_dev = torch.from_numpy(x).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for label, levels in (("derived", 0), ("stored", 1)):
+        s = ax.encode(x, threads=HOST_THREADS, levels=levels, **wl["enc"])
+        ds = ax.to_device(s, dev)
+        out = torch.empty(ds.n, dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(ax.workspace_bytes([ds]), 256), dtype=torch.uint8, device=dev)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+        def step():
+            ax.decode(ds, out=out, workspace=ws, status=status, stream=stream)
+
+        step()
+        torch.cuda.synchronize()
+        ax.check_status(status)
+        mism, first = ax.compare(out, x_dev, stream=stream)
+        assert mism == 0, f"{label}: {mism} bytes differ, first at {first}"
+        ms = _timed(step, args.steps, args.warmup, stream)
+        ax.check_status(status)
+        assert ax.compare(out, x_dev, stream=stream)[0] == 0
+        res[label] = {"ms_per_decode": round(ms, 4), "gbps": round(ds.n / (ms * 1e-3) / 1e9, 2),
+                      "stream_bytes": int(s.size), "max_level": int(ds.info.max_level)}
+        del ds, out, ws
+        _free_gpu()
+    line = base_line(res["derived"]["gbps"], args.steps, args.warmup, res["derived"]["ms_per_decode"])
+    line["metric"] = "decoded GB/s with levels derived on the device (four-section streams)"
+    line["config"] = {"workload": wl["desc"] + "; encoded without stored levels"}
+    line["derive"] = res
+    print(json.dumps(line), flush=True)
+
+
 def run_batched(args):
     b = measure_batched(args)
     line = base_line(b["gbps"], max(1, min(args.steps, args.batched_steps)), 1, b["ms_per_call"])
@@ -811,7 +860,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="full", choices=["full", "plain", "batched", "served", "sweep", "algorithmic", "entropy"])
+    ap.add_argument("--mode", default="full", choices=["full", "plain", "batched", "served", "sweep", "algorithmic", "entropy", "derive"])
     ap.add_argument("--workload", default="wiki1g", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plan", action="store_true", help="plain mode: skip the plan + graph leg")
@@ -831,7 +880,7 @@ def main():
               "with no communication", file=sys.stderr)
         sys.exit(2)
     {"full": run_full, "plain": run_plain, "batched": run_batched, "served": run_served, "sweep": run_sweep,
-     "algorithmic": print_algorithmic, "entropy": run_entropy}[args.mode](args)
+     "algorithmic": print_algorithmic, "entropy": run_entropy, "derive": run_derive}[args.mode](args)
 
 
 if __name__ == "__main__":

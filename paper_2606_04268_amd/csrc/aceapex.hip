@@ -139,7 +139,7 @@ struct Batch {
     uint32_t *dcur, *dmax;      // where the scan of its source resumes, 1 + highest level seen
     uint32_t *dq[2];            // matches to scan at the next level (two, by level parity)
     uint32_t *dready;           // matches found ready at this level
-    uint32_t *dpage;            // per 256 output bytes: first match whose dst is at or past it
+    uint32_t *dpage;            // per 2^PAGE_LOG2 output bytes: first match whose dst is at or past it
     uint32_t *dcnt;             // counters (DC_*)
 };
 
@@ -159,6 +159,7 @@ struct LevelArgs {
 };
 
 constexpr uint32_t NONE = 0xffffffffu;
+constexpr uint32_t PAGE_LOG2 = 5;  // derive: output bytes per page-index entry, log2
 constexpr uint32_t NO_SLOT = 0xffffffffu;  // k_parse: a level whose slots ran out
 
 // counters of the derive path
@@ -1230,11 +1231,12 @@ __device__ __forceinline__ uint32_t load_l2(const uint32_t *p)
 
 // The match that writes output byte b (of N), or NONE when a literal does;
 // run_end gets the end of the run of bytes that writer (or literal run)
-// covers.  B.dpage[b >> 8] is the first match whose destination is at or
-// past the start of b's 256-byte page.
+// covers.  B.dpage[b >> PAGE_LOG2] is the first match whose destination is
+// at or past the start of b's page; a page of 32 bytes holds a few matches,
+// so the walk from there is short.
 __device__ __forceinline__ uint32_t writer_of(const Batch &B, uint32_t b, uint32_t M, uint32_t N, uint32_t &run_end)
 {
-    uint32_t c = B.dpage[b >> 8];
+    uint32_t c = B.dpage[b >> PAGE_LOG2];
     while (c < M && B.recs[3ull * c] <= b) c++;  // c: the first match whose destination is past b
     if (c > 0) {
         const uint32_t *r = B.recs + 3ull * (c - 1);
@@ -1320,15 +1322,15 @@ __device__ __forceinline__ void derive_run(const Batch &B, uint32_t m, uint32_t 
     if ((threadIdx.x & 63) == 0 && ran) atomicAdd(&B.dcnt[DC_DONE], (uint32_t)__popcll(ran));
 }
 
-// Per 256-byte page of the output: the first match whose destination is at
-// or past the page's start.
+// Per page of the output (2^PAGE_LOG2 bytes): the first match whose
+// destination is at or past the page's start.
 __global__ void __launch_bounds__(NT) k_pages(Batch B)
 {
     if (*B.one.status) return;
-    const uint32_t M = B.n_seq, np = (B.one.n >> 8) + 1;
+    const uint32_t M = B.n_seq, np = (B.one.n >> PAGE_LOG2) + 1;
     for (uint32_t r = blockIdx.x * NT + threadIdx.x; r <= M; r += gridDim.x * NT) {
-        const uint32_t lo = r == 0 ? 0u : (B.recs[3ull * (r - 1)] >> 8) + 1;
-        const uint32_t hi = r == M ? np - 1 : B.recs[3ull * r] >> 8;
+        const uint32_t lo = r == 0 ? 0u : (B.recs[3ull * (r - 1)] >> PAGE_LOG2) + 1;
+        const uint32_t hi = r == M ? np - 1 : B.recs[3ull * r] >> PAGE_LOG2;
         for (uint32_t pg = lo; pg <= hi && pg < np; pg++) B.dpage[pg] = r;
     }
 }
@@ -1703,7 +1705,7 @@ WsDerive ws_derive(const aceapex_info &in)
     w.q0 = o; o = align256(o + m4);
     w.q1 = o; o = align256(o + m4);
     w.ready = o; o = align256(o + m4);
-    w.page = o; o = align256(o + 4 * ((size_t)(in.decoded_bytes >> 8) + 1));
+    w.page = o; o = align256(o + 4 * ((size_t)(in.decoded_bytes >> PAGE_LOG2) + 1));
     w.total = o;
     return w;
 }
