@@ -140,8 +140,10 @@ int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *cou
 /* Device workspace, in bytes, that aceapex_decode_many needs for these n
  * descriptors (n = 1 for aceapex_decode): per chunk a 64-byte descriptor of
  * its slices of the Sec. 3.2 streams, per level of Sec. 7.1 three slot
- * counters, and 12 bytes per match for the level-grouped match records; for
- * a stream without levels, the workspace of aceapex_decode_derive; with
+ * counters, and 12 bytes per match for the level-grouped match records
+ * (n = 1 and at most 64 levels: also 4 bytes per (level, chunk) for the
+ * ordered record slots described at aceapex_decode); for a stream without
+ * levels, the workspace of aceapex_decode_derive; with
  * ACEAPEX_VALIDATE_LEVELS set, a stream with levels needs the larger of its
  * own and the derive workspace.  Pure host code; returns 0 when a
  * descriptor's info is inconsistent. */
@@ -162,7 +164,17 @@ size_t aceapex_workspace_bytes(const aceapex_desc *h_descs, uint32_t n);
  * source bytes (Sec. 7.1); a stream that breaks this gets ACEAPEX_E_CORRUPT.
  * The check costs a derive-mode parse and one pass over the matches, and the
  * larger workspace stated above.  aceapex_decode_many, plans and
- * aceapex_decode_noalloc do not check. */
+ * aceapex_decode_noalloc do not check.
+ *
+ * Record order.  For a stream of at most 64 levels and at least 4M matches
+ * (2^22), each chunk's matches per level are counted and scanned before the
+ * parse, so that every level's match records lie in output order, which
+ * the level launches copy faster; other streams reserve their records'
+ * slots with atomics, in the order the chunks finish.  The environment
+ * variable ACEAPEX_ORDERED_SLOTS overrides the size rule for streams of at
+ * most 64 levels: "0" never, any other non-empty value always (read at each
+ * call of aceapex_decode and aceapex_decode_noalloc, and when a plan is
+ * made).  The decoded bytes and the status do not depend on it. */
 int aceapex_decode(const aceapex_stream *stream, void *d_out, uint64_t out_capacity,
                    void *d_workspace, size_t ws_bytes, int32_t *d_status, void *hip_stream);
 

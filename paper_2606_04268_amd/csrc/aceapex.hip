@@ -133,6 +133,11 @@ struct Batch {
     uint32_t xcd_parts;         // k_level: contiguous parts of a level's records (1..8)
     uint32_t has_sig;           // single stream: the host scheduled the levels from a table
     uint64_t level_sig;         //   whose signature (level_signature) is this
+    // ordered record slots (single stream, at most ORD_LEVELS levels): per
+    // (level, chunk) the count of its matches, then its first slot
+    uint32_t ordered;
+    uint32_t *ocnt;             // [levels * n_chunks], level-major
+    uint32_t *otile;            // [tiles] sums of OTILE elements of ocnt, then their offsets
     // levels derived on the device (single stream): per match, in stream order
     uint32_t *dlevel;           // level once run, NONE before
     uint32_t *dhead, *dnext;    // matches parked on a match (linked list through dnext)
@@ -161,6 +166,9 @@ struct LevelArgs {
 constexpr uint32_t NONE = 0xffffffffu;
 constexpr uint32_t PAGE_LOG2 = 5;  // derive: output bytes per page-index entry, log2
 constexpr uint32_t NO_SLOT = 0xffffffffu;  // k_parse: a level whose slots ran out
+constexpr uint32_t ORD_LEVELS = 64;          // single streams with at most this many levels get ordered slots
+constexpr uint64_t ORD_MIN_SEQ = 1ull << 22;  // ... and at least this many matches (unless asked for)
+constexpr uint32_t OTILE = 4096;             // elements of ocnt per tile of its scan
 
 // counters of the derive path
 constexpr uint32_t DC_Q = 0;      // [2] matches queued to scan, by level parity
@@ -565,9 +573,10 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
             (void)wg_excl_scan64(i <= j.max_level ? level_mix(i, c) : 0, tmp, mixed);
             if (i <= j.max_level) {
                 const uint32_t lo = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
+                const uint32_t hi = (uint32_t)min(carry + ex + c, (uint64_t)j.n_seq);
                 B.rec_lo[i] = lo;
-                B.cursor[i] = lo;
-                B.rec_hi[i] = (uint32_t)min(carry + ex + c, (uint64_t)j.n_seq);
+                B.cursor[i] = B.ordered ? hi : lo;  // ordered slots are placed, not appended
+                B.rec_hi[i] = hi;
             }
             carry += tot;
             sig += mixed;
@@ -707,15 +716,17 @@ struct ParseLds {
     uint32_t bad;
 } __attribute__((aligned(16)));
 
-template <bool BATCH, uint32_t LH, uint32_t STAGE>
+// ORD: a single stream with ordered slots (its chunks' first slots per level
+// were counted and scanned before the parse).
+template <bool BATCH, uint32_t LH, uint32_t STAGE, bool ORD>
 __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
 {
     __shared__ ParseLds<LH, STAGE> L;
     const uint32_t t = threadIdx.x, wave = t >> 6;
     // Chunks in dispatch order: workgroups finish roughly in that order, so
-    // each level's records are appended roughly in output order and every
-    // contiguous part of a level that k_level gives one XCD covers one
-    // stretch of the output.
+    // each level's records are appended roughly in output order (exactly so
+    // with ordered slots) and every contiguous part of a level that k_level
+    // gives one XCD covers one stretch of the output.
     const uint32_t g = blockIdx.x;  // global chunk
     const uint32_t sj = BATCH ? B.chunk_job[g] : 0u;     // its stream
     const Job &j = BATCH ? B.jobs[sj] : B.one;
@@ -1046,23 +1057,33 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
         }
     }
     __syncthreads();
-    // one global atomic per level present in the chunk, all issued before
-    // any returns; a level whose reserved slots would pass its end (more
-    // matches than the level table announced) gets no records
+    // the first slot of each level present in the chunk: with ordered slots
+    // the chunk's own (counted and scanned before the parse, so that a
+    // level's records follow the chunks' order), else one global atomic per
+    // level, all issued before any returns.  A level whose slots would leave
+    // its range (more matches than the level table announced) gets no
+    // records.
     {
         constexpr uint32_t NI = (LH + NT - 1) / NT;
         uint32_t got[NI], cap[NI];
 #pragma unroll
         for (uint32_t k = 0; k < NI; k++) {
             const uint32_t i = t + k * NT;
-            const uint32_t c = i < nl ? L.lcount[i] : 0u;
-            got[k] = c ? atomicAdd(&B.cursor[j.lv0 + i], c) : 0u;
-            cap[k] = c ? B.rec_hi[j.lv0 + i] : 0u;
+            const uint32_t cn = i < nl ? L.lcount[i] : 0u;
+            if (ORD)
+                got[k] = cn ? B.ocnt[(size_t)i * j.n_chunks + c] : 0u;
+            else
+                got[k] = cn ? atomicAdd(&B.cursor[j.lv0 + i], cn) : 0u;
+            cap[k] = cn ? B.rec_hi[j.lv0 + i] : 0u;
         }
 #pragma unroll
         for (uint32_t k = 0; k < NI; k++) {
             const uint32_t i = t + k * NT;
-            if (i < nl && L.lcount[i]) L.lbase[i] = got[k] + L.lcount[i] <= cap[k] ? got[k] : NO_SLOT;
+            // an appended base never lies below the level's first slot; a
+            // placed one is checked against it too
+            const bool above = !ORD || got[k] >= B.rec_lo[j.lv0 + i];
+            if (i < nl && L.lcount[i])
+                L.lbase[i] = above && got[k] <= cap[k] && L.lcount[i] <= cap[k] - got[k] ? got[k] : NO_SLOT;
         }
     }
     __syncthreads();
@@ -1085,12 +1106,136 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
 template <bool BATCH>
 void launch_parse(const Batch &B, uint32_t grid, hipStream_t st)
 {
-    if (B.max_level < 256)
-        hipLaunchKernelGGL((k_parse<BATCH, 256, 7680>), dim3(grid), dim3(NT), 0, st, B);
+    static_assert(ORD_LEVELS <= 256, "ordered slots use the shallow parse shape");
+    if (!BATCH && B.ordered)
+        hipLaunchKernelGGL((k_parse<false, 256, 7680, true>), dim3(grid), dim3(NT), 0, st, B);
+    else if (B.max_level < 256)
+        hipLaunchKernelGGL((k_parse<BATCH, 256, 7680, false>), dim3(grid), dim3(NT), 0, st, B);
     else if (B.max_level < 1024)
-        hipLaunchKernelGGL((k_parse<BATCH, 1024, 1536>), dim3(grid), dim3(NT), 0, st, B);
+        hipLaunchKernelGGL((k_parse<BATCH, 1024, 1536, false>), dim3(grid), dim3(NT), 0, st, B);
     else
-        hipLaunchKernelGGL((k_parse<BATCH, 4096, 0>), dim3(grid), dim3(NT), 0, st, B);
+        hipLaunchKernelGGL((k_parse<BATCH, 4096, 0, false>), dim3(grid), dim3(NT), 0, st, B);
+}
+
+// ---------------------------------------------------- ordered record slots
+
+// A single stream with few levels gets its record slots in chunk order: each
+// chunk's matches of a level go to the slots after those of the chunks
+// before it, so that a level's records follow the output, as its copies'
+// destinations do (the level launches then write nearby lines together).
+// k_count counts each chunk's matches per level, k_otiles, k_otscan and
+// k_oapply turn the level-major counts into first slots (an exclusive scan
+// whose running total passes through each level's first slot), and k_parse
+// reads its chunk's first slots instead of taking them with atomics.
+
+// One wave per chunk: its matches per level into ocnt[level * C + chunk].
+// A malformed level section counts nothing (k_parse fails the stream).
+// Lanes count into HCOPIES histograms by lane (rows padded to a bank
+// offset), so that a run of equal levels among a wave's values does not
+// serialise on one LDS address.
+constexpr uint32_t HCOPIES = 4;
+__global__ void __launch_bounds__(NT) k_count(Batch B)
+{
+    __shared__ uint32_t vals[NT / 64][K_MAX];
+    __shared__ uint32_t hist[NT / 64][HCOPIES][ORD_LEVELS + 1];
+    static_assert(ORD_LEVELS <= 64, "one lane per level");
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const Job &j = B.one;
+    const uint32_t C = j.n_chunks, nl = j.max_level + 1, K = 1u << j.chunk_log2;
+    const uint32_t c = blockIdx.x * (NT / 64) + wave;  // the same on every lane of the wave
+    if (c >= C) return;  // no workgroup barrier below: each wave works alone
+    uint32_t *const h = &hist[wave][0][0];
+    for (uint32_t i = lane; i < HCOPIES * (ORD_LEVELS + 1); i += 64) h[i] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the wave's LDS accesses stay in program order
+    uint32_t *const mine = h + (lane % HCOPIES) * (ORD_LEVELS + 1);
+    const ChunkDesc d = j.chunks[c];
+    const uint32_t ns = d.nseq_last & 0x7fffffffu;
+    if (desc_in_bounds(j, d, K) && (d.out_base >> j.block_log2) < j.n_blocks) {
+        if (d.lvl_n == ns) {  // one byte per level: every load issued before the first count
+            constexpr uint32_t ROUNDS = K_MAX / (4 * 64);
+            uint32_t w4[ROUNDS];
+#pragma unroll
+            for (uint32_t r = 0; r < ROUNDS; r++) {
+                const uint32_t e = 4 * lane + 4 * 64 * r;
+                w4[r] = e < ns ? bytes4(j.comp + d.lvl_at, e, ns) : 0u;
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < ROUNDS; r++) {
+                const uint32_t e = 4 * lane + 4 * 64 * r;
+#pragma unroll
+                for (uint32_t k = 0; k < 4; k++) {
+                    const uint32_t v = (w4[r] >> (8 * k)) & 0xffu;
+                    if (e + k < ns && v < nl) atomicAdd(&mine[v], 1u);
+                }
+            }
+        } else if (wave_varints(j.comp + d.lvl_at, d.lvl_n, j.comp_bytes - d.lvl_at, ns, vals[wave])) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            for (uint32_t e = lane; e < ns; e += 64) {
+                const uint32_t v = vals[wave][e];
+                if (v < nl) atomicAdd(&mine[v], 1u);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane < nl) {
+        uint32_t cnt = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < HCOPIES; k++) cnt += h[k * (ORD_LEVELS + 1) + lane];
+        B.ocnt[(size_t)lane * C + c] = cnt;
+    }
+}
+
+// The sum of each OTILE elements of ocnt.
+__global__ void __launch_bounds__(NT) k_otiles(Batch B)
+{
+    __shared__ uint64_t tmp[NT / 64];
+    const uint64_t E = (uint64_t)(B.one.max_level + 1) * B.one.n_chunks, t0 = (uint64_t)blockIdx.x * OTILE;
+    const uint64_t t1 = min(E, t0 + OTILE);
+    uint64_t sum = 0, tot;
+    for (uint64_t i = t0 + threadIdx.x; i < t1; i += NT) sum += B.ocnt[i];
+    (void)wg_excl_scan64(sum, tmp, tot);
+    if (threadIdx.x == 0) B.otile[blockIdx.x] = (uint32_t)tot;
+}
+
+// One workgroup: the tile sums become the tiles' first slots.
+__global__ void __launch_bounds__(NT) k_otscan(Batch B, uint32_t ntiles)
+{
+    __shared__ uint64_t tmp[NT / 64];
+    uint64_t carry = 0;
+    for (uint32_t s0 = 0; s0 < ntiles; s0 += NT) {
+        const uint32_t i = s0 + threadIdx.x;
+        const uint64_t v = i < ntiles ? B.otile[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = wg_excl_scan64(v, tmp, tot);
+        if (i < ntiles) B.otile[i] = (uint32_t)(carry + ex);
+        carry += tot;
+    }
+}
+
+// Each count becomes its first slot.  The element of each level's first
+// chunk must land on the level's first slot and the last one must end at
+// the last slot, else the stream's chunks and its level table disagree and
+// the decode fails.
+__global__ void __launch_bounds__(NT) k_oapply(Batch B)
+{
+    __shared__ uint64_t tmp[NT / 64];
+    const uint32_t C = B.one.n_chunks, nl = B.one.max_level + 1;
+    const uint64_t E = (uint64_t)nl * C, t0 = (uint64_t)blockIdx.x * OTILE;
+    const uint64_t t1 = min(E, t0 + OTILE);
+    uint64_t carry = B.otile[blockIdx.x];
+    for (uint64_t s0 = t0; s0 < t1; s0 += NT) {
+        const uint64_t i = s0 + threadIdx.x;
+        const uint64_t v = i < t1 ? B.ocnt[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = wg_excl_scan64(v, tmp, tot);
+        if (i < t1) {
+            const uint64_t at = carry + ex;
+            B.ocnt[i] = (uint32_t)at;
+            if (i % C == 0 && at != B.rec_lo[i / C]) fail(B.one, ACEAPEX_E_CORRUPT);
+            if (i == E - 1 && at + v != B.rec_hi[nl - 1]) fail(B.one, ACEAPEX_E_CORRUPT);
+        }
+        carry += tot;
+    }
 }
 
 // --------------------------------------------------------------- k_seal
@@ -1129,7 +1274,10 @@ __global__ void __launch_bounds__(NT) k_seal(Batch B)
 // first level launch (check != 0) compares every level's fill cursor with
 // the level's end and fails the decode when a slot was left unfilled, which
 // only a corrupt stream can do; such a slot's stale record is still bounds-
-// checked like any other.
+// checked like any other.  With ordered slots the cursors start at the
+// levels' ends; k_oapply has checked that the chunks' counts tile every
+// level's range, and a chunk whose parse leaves its slots unfilled fails
+// the decode itself.
 template <bool BATCH, uint32_t R>
 __global__ void __launch_bounds__(NT) k_level(LevelArgs B, uint32_t k, uint32_t lo, uint32_t hi, uint32_t check)
 {
@@ -1585,8 +1733,32 @@ void launch_levels(const Batch &B, const C *counts, uint64_t n_seq, const Tune &
 // ---- one stream
 
 struct WsLayout {
-    size_t status, chunks, blk_ok, rec_lo, rec_hi, cursor, recs, total;
+    size_t status, chunks, blk_ok, rec_lo, rec_hi, cursor, recs, ocnt, otile, total;
 };
+
+// Ordered record slots apply to streams with stored levels and at most
+// ORD_LEVELS of them, whose workspace always holds the counts.  They are
+// used for such streams of at least ORD_MIN_SEQ matches: on smaller ones the
+// four extra launches cost more than the order saves (the 4 MiB Markov
+// text, 0.68M matches: 0.114 -> 0.131 ms).  ACEAPEX_ORDERED_SLOTS, read at
+// each call, overrides that: "0" never, anything else non-empty always.
+bool ordered_eligible(const aceapex_info &in)
+{
+    return has_table(in) && in.max_level + 1u <= ORD_LEVELS && in.n_chunks > 0 && in.n_seq > 0;
+}
+
+bool ordered_slots(const aceapex_info &in)
+{
+    if (!ordered_eligible(in)) return false;
+    const char *v = getenv("ACEAPEX_ORDERED_SLOTS");
+    if (v && v[0]) return strcmp(v, "0") != 0;
+    return in.n_seq >= ORD_MIN_SEQ;
+}
+
+uint64_t ord_tiles(const aceapex_info &in)
+{
+    return ((uint64_t)(in.max_level + 1) * in.n_chunks + OTILE - 1) / OTILE;
+}
 
 WsLayout ws_single(const aceapex_info &in)
 {
@@ -1600,6 +1772,9 @@ WsLayout ws_single(const aceapex_info &in)
     w.rec_hi = o; o = align256(o + 4 * nl);
     w.cursor = o; o = align256(o + 4 * nl);
     w.recs = o; o = align256(o + 12ull * (size_t)in.n_seq);
+    const bool ord = ordered_eligible(in);
+    w.ocnt = o; o = align256(o + (ord ? 4 * nl * (size_t)in.n_chunks : 0));
+    w.otile = o; o = align256(o + (ord ? 4 * (size_t)ord_tiles(in) : 0));
     w.total = o;
     return w;
 }
@@ -1654,6 +1829,9 @@ void single_batch(const aceapex_stream &s, void *d_out, uint8_t *ws, int32_t *d_
     B.rec_hi = (uint32_t *)(ws + w.rec_hi);
     B.cursor = (uint32_t *)(ws + w.cursor);
     B.recs = (uint32_t *)(ws + w.recs);
+    B.ordered = ordered_slots(in) ? 1u : 0u;
+    B.ocnt = (uint32_t *)(ws + w.ocnt);
+    B.otile = (uint32_t *)(ws + w.otile);
     B.n_jobs = 1;
     B.n_blocks = in.n_blocks;
     B.n_chunks = in.n_chunks;
@@ -1972,6 +2150,13 @@ void enqueue_single(Batch B, const C *counts, const Tune &tn, hipStream_t st, bo
     if (B.n_blocks) {
         {
             PhaseScope ps(PH_PARSE, st, timed);
+            if (B.ordered) {  // the chunks' first slots per level, before the parse
+                const uint32_t tiles = (uint32_t)(((uint64_t)(B.max_level + 1) * B.n_chunks + OTILE - 1) / OTILE);
+                hipLaunchKernelGGL(k_count, dim3((B.n_chunks + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, st, B);
+                hipLaunchKernelGGL(k_otiles, dim3(tiles), dim3(NT), 0, st, B);
+                hipLaunchKernelGGL(k_otscan, dim3(1), dim3(NT), 0, st, B, tiles);
+                hipLaunchKernelGGL(k_oapply, dim3(tiles), dim3(NT), 0, st, B);
+            }
             launch_parse<false>(B, B.n_chunks, st);
         }
         if (B.n_seq) launch_levels(B, counts, B.n_seq, tn, st, timed);

@@ -157,6 +157,31 @@ def test_workspace_follows_level_validation(monkeypatch):
     assert checked == max(plain, _abi.workspace_bytes_derive(info)) and checked > plain
 
 
+def test_workspace_holds_ordered_slot_counts(monkeypatch):
+    """A stream of at most 64 levels has room for its (level, chunk) counts
+    whatever ACEAPEX_ORDERED_SLOTS says (the setting is read at each decode);
+    a deeper stream has none."""
+    x = synth.wiki(8 << 20, 0xACE5)
+    ws = {}
+    for depth in (64, 65):
+        info = _abi.probe(oracle.encode(x, block_log2=20, max_depth=depth))
+        assert info.max_level == depth - 1
+        desc = [_abi.Desc(_abi.Stream(0, info, None), 0, info.decoded_bytes, 0)]
+        sizes = set()
+        for v in (None, "0", "1"):
+            if v is None:
+                monkeypatch.delenv("ACEAPEX_ORDERED_SLOTS", raising=False)
+            else:
+                monkeypatch.setenv("ACEAPEX_ORDERED_SLOTS", v)
+            sizes.add(_abi.workspace_bytes(desc))
+        assert len(sizes) == 1
+        ws[depth] = (sizes.pop(), info)
+    (w64, i64), (w65, i65) = ws[64], ws[65]
+    assert i64.n_chunks == i65.n_chunks and abs(i64.n_seq - i65.n_seq) < 100
+    # the two layouts differ otherwise by a few KiB (level counters, alignment)
+    assert 4 * 64 * i64.n_chunks - 8192 <= w64 - w65 <= 4 * 64 * i64.n_chunks + 8192
+
+
 def test_compare_argument_errors_need_no_gpu():
     """aceapex_compare refuses a null or misaligned result pointer and null
     buffers before it touches the GPU."""

@@ -64,7 +64,7 @@ def test_config0_markov_4mib():
 @pytest.mark.parametrize("opts", [dict(), dict(flatten=1), dict(max_depth=8), dict(flatten=2),
                                   dict(tiebreak=1)],
                          ids=["plain", "flat", "d8", "flatlit", "recent"])
-def test_generated_kinds(kind, opts):
+def test_generated_kinds(kind, opts, ordered_slots):
     x = synth.make(kind, 3 << 19, 0xACE0 + len(kind))
     s = oracle.encode(x, block_log2=18, **opts)
     parity(x, s, f"{kind}/{opts}")
@@ -72,14 +72,14 @@ def test_generated_kinds(kind, opts):
 
 @pytest.mark.parametrize("chunk_log2", [0, 3, 7, 10])
 @pytest.mark.parametrize("block_log2", [3, 9, 16, 20])
-def test_block_and_chunk_sizes(block_log2, chunk_log2):
+def test_block_and_chunk_sizes(block_log2, chunk_log2, ordered_slots):
     x = synth.markov(200_000 + 1234, 77)
     s = oracle.encode(x, block_log2=block_log2, chunk_log2=chunk_log2, hash_bits=16)
     parity(x, s, f"bl{block_log2}/ck{chunk_log2}")
 
 
 @pytest.mark.parametrize("seed", range(16))
-def test_random_token_streams(seed):
+def test_random_token_streams(seed, ordered_slots):
     rng = np.random.default_rng(100 + seed)
     bl = [3, 4, 6, 10, 14, 20][seed % 6]
     n = int(rng.integers(1, 60_000))
@@ -90,7 +90,7 @@ def test_random_token_streams(seed):
 
 
 @pytest.mark.parametrize("width", [4, "random"])
-def test_padded_varints(width):
+def test_padded_varints(width, ordered_slots):
     """Non-minimal LEB128: every value padded to 4 bytes fills a full chunk's
     slices to 4096 bytes (the largest the workgroup decoder takes) and a
     chunk that also holds the trailing run to 4100 (decoded one wave per
@@ -108,7 +108,7 @@ def test_padded_varints(width):
     parity(np.frombuffer(want, np.uint8), s, f"padded varints random tokens width={width}")
 
 
-def test_long_literal_runs_in_staged_chunks():
+def test_long_literal_runs_in_staged_chunks(ordered_slots):
     """Chunks whose literals are staged in LDS, with the run-length patterns
     that select each way of placing the words past a run's first four: a few
     very long runs in a wave (placed by the whole wave, several 256-byte steps
@@ -160,14 +160,14 @@ def test_level_chains_of_every_histogram_shape(m):
     parity(np.frombuffer(want, np.uint8), s, f"chain{m}")
 
 
-def test_edge_cases():
+def test_edge_cases(ordered_slots):
     for x in [b"", b"a", b"abc", b"abcd" * 3, bytes(range(256)), b"z" * 70_000]:
         for o in [dict(), dict(block_log2=3, chunk_log2=0), dict(flatten=1, block_log2=4)]:
             s = oracle.encode(x, hash_bits=10, **o)
             parity(np.frombuffer(x, np.uint8), s, f"edge n={len(x)} {o}")
 
 
-def test_multiple_of_chunk_size():
+def test_multiple_of_chunk_size(ordered_slots):
     blocks = [([(4, 4, 0)] * 8, 3)]
     lits = bytes(range(35))
     n = 8 * 8 + 3
@@ -260,3 +260,26 @@ def test_many_blocks_many_levels():
     s, want = streamgen.build(blocks, bytes(range(8)), n, block_log2=3, chunk_log2=2)
     assert oracle.header_fields(s)["max_level"] == m - 1
     parity(np.frombuffer(want, np.uint8), s, "chain-of-blocks")
+
+
+@pytest.mark.parametrize("depth", [63, 64, 65])
+def test_ordered_slots_level_limit(depth, ordered_slots):
+    """Streams of 63, 64 and 65 levels: single streams of at most 64 levels
+    place each chunk's records at slots counted and scanned before the parse,
+    deeper ones append them; both must decode the same bytes."""
+    x = synth.wiki(8 << 20, 0xACE5)  # 72 levels at unlimited depth
+    s = oracle.encode(x, block_log2=20, max_depth=depth)
+    assert oracle.header_fields(s)["max_level"] == depth - 1
+    parity(x, s, f"depth{depth}")
+
+
+def test_ordered_slots_scan_over_many_tiles(ordered_slots):
+    """Eight sequences per chunk and about 40 levels: more (level, chunk)
+    counts than one workgroup's pass of the tile scan covers (over 256 tiles
+    of 4096 counts, the last one partial)."""
+    x = synth.wiki(6 << 20, 0xACE6)
+    s = oracle.encode(x, block_log2=20, chunk_log2=3, max_depth=40)
+    h = oracle.header_fields(s)
+    assert h["max_level"] == 39 and (h["max_level"] + 1) * h["n_chunks"] > 256 * 4096
+    assert (h["max_level"] + 1) * h["n_chunks"] % 4096 != 0
+    parity(x, s, "ordered-many-tiles")

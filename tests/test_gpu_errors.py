@@ -21,6 +21,13 @@ def _gpu():
     yield
 
 
+@pytest.fixture(autouse=True)
+def _both_slot_orders(ordered_slots):
+    """Every corrupt stream fails with slots reserved by atomics and with
+    ordered slots."""
+    yield
+
+
 BL, CK = 10, 3  # 1 KiB blocks, 8 sequences per chunk
 
 

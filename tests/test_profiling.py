@@ -18,6 +18,9 @@ K = {
     "level1": "void (anonymous namespace)::k_level<false, 1u>((anonymous namespace)::Batch, unsigned int)",
     "level2": "void (anonymous namespace)::k_level<false, 2u>((anonymous namespace)::Batch, unsigned int)",
     "tail": "void (anonymous namespace)::k_tail<false>((anonymous namespace)::Batch, unsigned int)",
+    "count": "(anonymous namespace)::k_count((anonymous namespace)::Batch)",
+    "oapply": "(anonymous namespace)::k_oapply((anonymous namespace)::Batch)",
+    "parse_ord": "void (anonymous namespace)::k_parse<false, 256u, 7680u, true>((anonymous namespace)::Batch)",
     "copy": "__amd_rocclr_copyBuffer",
     "other": "void at::native::vectorized_elementwise_kernel<16, at::native::FillFunctor<unsigned char>>(int)",
 }
@@ -49,6 +52,17 @@ def test_kernel_names_and_groups():
     assert profiling._label(K["setup"]) == "k_setup"
     assert profiling._short(K["copy"]) == "__amd_rocclr_copyBuffer"
     assert {profiling.GROUP_OF[profiling._short(K[k])] for k in ("level1", "level2", "tail")} == {"levels"}
+
+
+def test_ordered_slot_kernels_count_as_parse(tmp_path):
+    """The slot count and scan kernels before an ordered-slot parse belong to
+    the parse group of the same decode."""
+    assert profiling._label(K["parse_ord"]) == "k_parse<false, 256u, 7680u, true>"
+    one = [("setup", 10), ("count", 40), ("oapply", 5), ("parse_ord", 900), ("level2", 300), ("tail", 5)]
+    d = write_counters(str(tmp_path / "fetch"), "FETCH_SIZE", one + one)
+    r = profiling.per_decode(d, "FETCH_SIZE")
+    assert r["decodes"] == 2 and r["dispatches_per_decode"] == 6
+    assert r["parse"] == pytest.approx(945) and r["levels"] == pytest.approx(305)
 
 
 def test_calibration_scales_a_copy_of_one_gib_to_one_gib(tmp_path):
