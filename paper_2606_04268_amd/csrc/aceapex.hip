@@ -166,6 +166,7 @@ struct LevelArgs {
 constexpr uint32_t NONE = 0xffffffffu;
 constexpr uint32_t PAGE_LOG2 = 5;  // derive: output bytes per page-index entry, log2
 constexpr uint32_t NO_SLOT = 0xffffffffu;  // k_parse: a level whose slots ran out
+constexpr uint32_t CUR_STRIDE = 32;  // single stream: words per level cursor (one 128-byte line each)
 constexpr uint32_t ORD_LEVELS = 64;          // single streams with at most this many levels get ordered slots
 constexpr uint64_t ORD_MIN_SEQ = 1ull << 22;  // ... and at least this many matches (unless asked for)
 constexpr uint32_t OTILE = 4096;             // elements of ocnt per tile of its scan
@@ -328,7 +329,7 @@ __device__ __forceinline__ void level_range(const A &B, uint32_t k, uint32_t &lo
         hi = B.level_lo[k + 1];
     } else {
         lo = B.rec_lo[k];
-        hi = min(B.cursor[k], B.rec_hi[k]);
+        hi = min(B.cursor[(size_t)k * CUR_STRIDE], B.rec_hi[k]);
     }
 }
 
@@ -575,7 +576,7 @@ __global__ void __launch_bounds__(NT) k_setup(Batch B)
                 const uint32_t lo = (uint32_t)min(carry + ex, (uint64_t)j.n_seq);
                 const uint32_t hi = (uint32_t)min(carry + ex + c, (uint64_t)j.n_seq);
                 B.rec_lo[i] = lo;
-                B.cursor[i] = B.ordered ? hi : lo;  // ordered slots are placed, not appended
+                B.cursor[(size_t)i * CUR_STRIDE] = B.ordered ? hi : lo;  // ordered slots are placed, not appended
                 B.rec_hi[i] = hi;
             }
             carry += tot;
@@ -1047,7 +1048,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
             rank[u] = atomicAdd(&L.lcount[l[u]], 1u);
         } else {
             const uint32_t e = j.lv0 + l[u];
-            const uint32_t slot = atomicAdd(&B.cursor[e], 1u);
+            const uint32_t slot = atomicAdd(&B.cursor[BATCH ? e : (size_t)e * CUR_STRIDE], 1u);
             if (slot < B.rec_hi[e]) {
                 uint32_t *rr = B.recs + 3ull * slot;
                 rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u] | tag;
@@ -1073,7 +1074,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
             if (ORD)
                 got[k] = cn ? B.ocnt[(size_t)i * j.n_chunks + c] : 0u;
             else
-                got[k] = cn ? atomicAdd(&B.cursor[j.lv0 + i], cn) : 0u;
+                got[k] = cn ? atomicAdd(&B.cursor[BATCH ? j.lv0 + i : (size_t)i * CUR_STRIDE], cn) : 0u;
             cap[k] = cn ? B.rec_hi[j.lv0 + i] : 0u;
         }
 #pragma unroll
@@ -1285,7 +1286,7 @@ __global__ void __launch_bounds__(NT) k_level(LevelArgs B, uint32_t k, uint32_t 
     if (lo == NO_RANGE) level_range(B, k, R0, R1);
     if (!BATCH && check && blockIdx.x == 0) {
         for (uint32_t i = threadIdx.x; i <= B.one.max_level; i += blockDim.x)
-            if (B.cursor[i] != B.rec_hi[i]) atomicCAS(B.one.status, 0, ACEAPEX_E_CORRUPT);
+            if (B.cursor[(size_t)i * CUR_STRIDE] != B.rec_hi[i]) atomicCAS(B.one.status, 0, ACEAPEX_E_CORRUPT);
     }
     const uint32_t G = gridDim.x, P = G < B.xcd_parts ? G : B.xcd_parts;
     const uint32_t x = blockIdx.x % P, w = blockIdx.x / P, W = (G - x + P - 1) / P;
@@ -1770,7 +1771,7 @@ WsLayout ws_single(const aceapex_info &in)
     w.blk_ok = o; o = align256(o + (size_t)in.n_blocks);
     w.rec_lo = o; o = align256(o + 4 * nl);
     w.rec_hi = o; o = align256(o + 4 * nl);
-    w.cursor = o; o = align256(o + 4 * nl);
+    w.cursor = o; o = align256(o + 4 * CUR_STRIDE * nl);
     w.recs = o; o = align256(o + 12ull * (size_t)in.n_seq);
     const bool ord = ordered_eligible(in);
     w.ocnt = o; o = align256(o + (ord ? 4 * nl * (size_t)in.n_chunks : 0));
