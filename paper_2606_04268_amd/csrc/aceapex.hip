@@ -1058,47 +1058,123 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
         }
     }
     __syncthreads();
-    // the first slot of each level present in the chunk: with ordered slots
-    // the chunk's own (counted and scanned before the parse, so that a
-    // level's records follow the chunks' order), else one global atomic per
-    // level, all issued before any returns.  A level whose slots would leave
-    // its range (more matches than the level table announced) gets no
-    // records.
-    {
+    if constexpr (LH >= 1024) {
+        // Deep streams, whose chunks spread their matches over tens of
+        // levels: the records go out grouped by level.  Each is first put in
+        // LDS (the tile, free by now) at its level's first position among the
+        // chunk's records plus its rank, then the workgroup writes them in
+        // that order, so that neighbouring lanes write neighbouring slots of
+        // one level; written straight from each match, a store instruction
+        // would touch as many separate regions as it has levels.  (On streams
+        // of few levels per chunk the extra barriers cost more than this
+        // saves.)  Thread t scans the counts of levels t*NI .. t*NI+NI-1;
+        // each level's first position then replaces its count in lcount.
         constexpr uint32_t NI = (LH + NT - 1) / NT;
-        uint32_t got[NI], cap[NI];
+        static_assert(TILE_BYTES >= 16 * K_MAX, "a chunk's records fit the tile");
+        uint4 *const grp = (uint4 *)L.u.tile;
+        uint32_t grouped;  // the chunk's matches of levels below LH
+        {
+            uint32_t cnt[NI], own = 0;
 #pragma unroll
-        for (uint32_t k = 0; k < NI; k++) {
-            const uint32_t i = t + k * NT;
-            const uint32_t cn = i < nl ? L.lcount[i] : 0u;
-            if (ORD)
-                got[k] = cn ? B.ocnt[(size_t)i * j.n_chunks + c] : 0u;
-            else
-                got[k] = cn ? atomicAdd(&B.cursor[BATCH ? j.lv0 + i : (size_t)i * CUR_STRIDE], cn) : 0u;
-            cap[k] = cn ? B.rec_hi[j.lv0 + i] : 0u;
-        }
+            for (uint32_t k = 0; k < NI; k++) {
+                cnt[k] = t * NI + k < nl ? L.lcount[t * NI + k] : 0u;
+                own += cnt[k];
+            }
+            uint64_t tot;
+            uint32_t at = (uint32_t)wg_excl_scan64(own, L.tmp, tot);  // its barriers end every read of lcount above
+            grouped = (uint32_t)tot;
 #pragma unroll
-        for (uint32_t k = 0; k < NI; k++) {
-            const uint32_t i = t + k * NT;
-            // an appended base never lies below the level's first slot; a
-            // placed one is checked against it too
-            const bool above = !ORD || got[k] >= B.rec_lo[j.lv0 + i];
-            if (i < nl && L.lcount[i])
-                L.lbase[i] = above && got[k] <= cap[k] && L.lcount[i] <= cap[k] - got[k] ? got[k] : NO_SLOT;
+            for (uint32_t k = 0; k < NI; k++) {
+                if (t * NI + k < nl) L.lcount[t * NI + k] = at;
+                at += cnt[k];
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (uint32_t u = 0; u < PER; u++) {
-        if (rank[u] == 0xffffffffu) continue;
-        const uint32_t lb = L.lbase[l[u]];
-        const uint32_t slot = lb + rank[u];
-        if (lb == NO_SLOT) {
-            bad = true;
-            continue;
+        for (uint32_t u = 0; u < PER; u++)
+            if (rank[u] != 0xffffffffu) grp[L.lcount[l[u]] + rank[u]] = make_uint4(dst[u], src[u], m[u] | tag, l[u]);
+        // the first slot of each level present in the chunk: with ordered slots
+        // the chunk's own (counted and scanned before the parse, so that a
+        // level's records follow the chunks' order), else one global atomic per
+        // level, all issued before any returns.  A level whose slots would leave
+        // its range (more matches than the level table announced) gets no
+        // records.  A level's count is the distance to the next level's first
+        // position.
+        {
+            uint32_t got[NI], cap[NI], cnt[NI];
+#pragma unroll
+            for (uint32_t k = 0; k < NI; k++) {
+                const uint32_t i = t + k * NT;
+                cnt[k] = i < nl ? (i + 1 < nl ? L.lcount[i + 1] : grouped) - L.lcount[i] : 0u;
+                if (ORD)
+                    got[k] = cnt[k] ? B.ocnt[(size_t)i * j.n_chunks + c] : 0u;
+                else
+                    got[k] = cnt[k] ? atomicAdd(&B.cursor[BATCH ? j.lv0 + i : (size_t)i * CUR_STRIDE], cnt[k]) : 0u;
+                cap[k] = cnt[k] ? B.rec_hi[j.lv0 + i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < NI; k++) {
+                const uint32_t i = t + k * NT;
+                // an appended base never lies below the level's first slot; a
+                // placed one is checked against it too
+                const bool above = !ORD || got[k] >= B.rec_lo[j.lv0 + i];
+                if (cnt[k]) L.lbase[i] = above && got[k] <= cap[k] && cnt[k] <= cap[k] - got[k] ? got[k] : NO_SLOT;
+            }
         }
-        uint32_t *rr = B.recs + 3ull * slot;
-        rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u] | tag;
+        __syncthreads();
+        for (uint32_t q = t; q < grouped; q += NT) {
+            const uint4 v = grp[q];
+            const uint32_t lb = L.lbase[v.w];
+            if (lb == NO_SLOT) {
+                bad = true;
+                continue;
+            }
+            uint32_t *rr = B.recs + 3ull * (lb + (q - L.lcount[v.w]));
+            rr[0] = v.x; rr[1] = v.y; rr[2] = v.z;
+        }
+    } else {
+        // the first slot of each level present in the chunk: with ordered slots
+        // the chunk's own (counted and scanned before the parse, so that a
+        // level's records follow the chunks' order), else one global atomic per
+        // level, all issued before any returns.  A level whose slots would leave
+        // its range (more matches than the level table announced) gets no
+        // records.
+        {
+            constexpr uint32_t NI = (LH + NT - 1) / NT;
+            uint32_t got[NI], cap[NI];
+#pragma unroll
+            for (uint32_t k = 0; k < NI; k++) {
+                const uint32_t i = t + k * NT;
+                const uint32_t cn = i < nl ? L.lcount[i] : 0u;
+                if (ORD)
+                    got[k] = cn ? B.ocnt[(size_t)i * j.n_chunks + c] : 0u;
+                else
+                    got[k] = cn ? atomicAdd(&B.cursor[BATCH ? j.lv0 + i : (size_t)i * CUR_STRIDE], cn) : 0u;
+                cap[k] = cn ? B.rec_hi[j.lv0 + i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < NI; k++) {
+                const uint32_t i = t + k * NT;
+                // an appended base never lies below the level's first slot; a
+                // placed one is checked against it too
+                const bool above = !ORD || got[k] >= B.rec_lo[j.lv0 + i];
+                if (i < nl && L.lcount[i])
+                    L.lbase[i] = above && got[k] <= cap[k] && L.lcount[i] <= cap[k] - got[k] ? got[k] : NO_SLOT;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t u = 0; u < PER; u++) {
+            if (rank[u] == 0xffffffffu) continue;
+            const uint32_t lb = L.lbase[l[u]];
+            const uint32_t slot = lb + rank[u];
+            if (lb == NO_SLOT) {
+                bad = true;
+                continue;
+            }
+            uint32_t *rr = B.recs + 3ull * slot;
+            rr[0] = dst[u]; rr[1] = src[u]; rr[2] = m[u] | tag;
+        }
     }
     if (bad) fail(j, ACEAPEX_E_CORRUPT);
 }

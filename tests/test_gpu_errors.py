@@ -141,6 +141,24 @@ def test_level_table_off_by_one():
     _expect_corrupt(s, "level table off by one")
 
 
+@pytest.mark.parametrize("where", ["first", "deep"])
+def test_level_table_off_by_one_deep_stream(where):
+    """A chain of 300 one-match levels in chunks of 32 sequences (the parse
+    shape for up to 1,024 levels, whose chunks write their records grouped
+    by level): the stream's level table moves one match from one level to
+    the next, so the parse finds a match at a level the table gives none."""
+    m = 300
+    blocks = [([(4, 4, 0)] + [(0, 4, 4 * i) for i in range(1, m)], 0)]
+    n = 4 + 4 * m
+    hist = [1] * m
+    k = 0 if where == "first" else 257
+    hist[k] -= 1
+    hist[k + 1] += 1
+    s, want = streamgen.build(blocks, b"abcd", n, block_log2=16, chunk_log2=5, level_counts=hist)
+    assert oracle.header_fields(s)["max_level"] == m - 1
+    _expect_corrupt(s, f"deep level table off by one at level {k}")
+
+
 def test_chunk_entry_past_its_section():
     _, _, _, s = _valid()
     sec = _sections(s, 1)
