@@ -123,6 +123,7 @@ struct Batch {
     const Job *jobs;            // device table of a batched decode, or nullptr
     uint32_t *blk_job;          // [n_blocks] global block -> stream (batched)
     uint32_t *chunk_job;        // [n_chunks] global chunk -> stream (batched)
+    const ChunkDesc *chunks_all;  // batched: every stream's chunk descriptors, by global chunk
     uint32_t *rec_lo, *rec_hi;  // per (stream, level): record slots [rec_lo, rec_hi)
     uint32_t *cursor;           // per (stream, level): next free slot
     const uint32_t *level_lo;   // [max_level + 2] slots of each level over the batch (batched)
@@ -730,6 +731,10 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     // gives one XCD covers one stretch of the output.
     const uint32_t g = blockIdx.x;  // global chunk
     const uint32_t sj = BATCH ? B.chunk_job[g] : 0u;     // its stream
+    // batched: the descriptor is read by its global index, beside the stream
+    // lookup rather than after it (one dependent load less per workgroup)
+    ChunkDesc d;
+    if constexpr (BATCH) d = B.chunks_all[g];
     const Job &j = BATCH ? B.jobs[sj] : B.one;
     const uint32_t c = g - j.c0;
     const uint32_t K = 1u << j.chunk_log2;
@@ -745,7 +750,7 @@ __global__ void __launch_bounds__(NT, BATCH ? 5 : 6) k_parse(Batch B)
     if (t < TILE_BYTES / 512) L.seg[t] = 0;
     __syncthreads();
     if (c >= j.n_chunks) return;
-    const ChunkDesc d = j.chunks[c];
+    if constexpr (!BATCH) d = j.chunks[c];
     const uint32_t blk = d.out_base >> j.block_log2;
     if (!desc_in_bounds(j, d, K) || blk >= j.n_blocks) {
         if (t == 0) fail(j, ACEAPEX_E_CORRUPT);
@@ -2196,6 +2201,7 @@ void build_group(const aceapex_desc *d, uint32_t n, uint8_t *ws, uint8_t *h, Gro
     B.jobs = (const Job *)(ws + w.jobs);
     B.blk_job = (uint32_t *)(ws + w.blk_job);
     B.chunk_job = (uint32_t *)(ws + w.chunk_job);
+    B.chunks_all = (const ChunkDesc *)(ws + w.chunks);
     B.rec_lo = (uint32_t *)(ws + w.rec_lo);
     B.rec_hi = (uint32_t *)(ws + w.rec_hi);
     B.cursor = (uint32_t *)(ws + w.cursor);
