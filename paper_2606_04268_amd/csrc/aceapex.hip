@@ -1205,65 +1205,93 @@ void launch_parse(const Batch &B, uint32_t grid, hipStream_t st)
 // chunk's matches of a level go to the slots after those of the chunks
 // before it, so that a level's records follow the output, as its copies'
 // destinations do (the level launches then write nearby lines together).
-// k_count counts each chunk's matches per level, k_otiles, k_otscan and
-// k_oapply turn the level-major counts into first slots (an exclusive scan
-// whose running total passes through each level's first slot), and k_parse
-// reads its chunk's first slots instead of taking them with atomics.
+// k_count counts each chunk's matches per level, k_otiles and k_oapply turn
+// the level-major counts into first slots (an exclusive scan whose running
+// total passes through each level's first slot; each k_oapply workgroup sums
+// the tile totals before its own), and k_parse reads its chunk's first slots
+// instead of taking them with atomics.
 
-// One wave per chunk: its matches per level into ocnt[level * C + chunk].
-// A malformed level section counts nothing (k_parse fails the stream).
-// Lanes count into HCOPIES histograms by lane (rows padded to a bank
-// offset), so that a run of equal levels among a wave's values does not
-// serialise on one LDS address.
+// One wave per CPW chunks: each chunk's matches per level into
+// ocnt[level * C + chunk].  A malformed level section counts nothing (k_parse
+// fails the stream).  Lanes count into HCOPIES histograms by lane (rows padded
+// to a bank offset), so that a run of equal levels among a wave's values does
+// not serialise on one LDS address.  The loads of both chunks (descriptors,
+// then their one-byte level words) are issued before the first count: the
+// kernel is bound by the latency of those two dependent loads.
 constexpr uint32_t HCOPIES = 4;
+constexpr uint32_t CPW = 2;
 __global__ void __launch_bounds__(NT) k_count(Batch B)
 {
     __shared__ uint32_t vals[NT / 64][K_MAX];
     __shared__ uint32_t hist[NT / 64][HCOPIES][ORD_LEVELS + 1];
     static_assert(ORD_LEVELS <= 64, "one lane per level");
+    constexpr uint32_t ROUNDS = K_MAX / (4 * 64);
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const Job &j = B.one;
     const uint32_t C = j.n_chunks, nl = j.max_level + 1, K = 1u << j.chunk_log2;
-    const uint32_t c = blockIdx.x * (NT / 64) + wave;  // the same on every lane of the wave
-    if (c >= C) return;  // no workgroup barrier below: each wave works alone
+    // the same on every lane of the wave: made scalar, so that descriptors
+    // are read by scalar loads into scalar registers
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane((blockIdx.x * (NT / 64) + wave) * CPW);
+    if (c0 >= C) return;  // no workgroup barrier below: each wave works alone
     uint32_t *const h = &hist[wave][0][0];
-    for (uint32_t i = lane; i < HCOPIES * (ORD_LEVELS + 1); i += 64) h[i] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the wave's LDS accesses stay in program order
     uint32_t *const mine = h + (lane % HCOPIES) * (ORD_LEVELS + 1);
-    const ChunkDesc d = j.chunks[c];
-    const uint32_t ns = d.nseq_last & 0x7fffffffu;
-    if (desc_in_bounds(j, d, K) && (d.out_base >> j.block_log2) < j.n_blocks) {
-        if (d.lvl_n == ns) {  // one byte per level: every load issued before the first count
-            constexpr uint32_t ROUNDS = K_MAX / (4 * 64);
-            uint32_t w4[ROUNDS];
+    ChunkDesc d[CPW];
+    uint32_t ns[CPW], kind[CPW], w4[CPW][ROUNDS];  // kind: 0 nothing to count, 1 one byte per level, 2 LEB128
 #pragma unroll
-            for (uint32_t r = 0; r < ROUNDS; r++) {
-                const uint32_t e = 4 * lane + 4 * 64 * r;
-                w4[r] = e < ns ? bytes4(j.comp + d.lvl_at, e, ns) : 0u;
-            }
-#pragma unroll
-            for (uint32_t r = 0; r < ROUNDS; r++) {
-                const uint32_t e = 4 * lane + 4 * 64 * r;
-#pragma unroll
-                for (uint32_t k = 0; k < 4; k++) {
-                    const uint32_t v = (w4[r] >> (8 * k)) & 0xffu;
-                    if (e + k < ns && v < nl) atomicAdd(&mine[v], 1u);
-                }
-            }
-        } else if (wave_varints(j.comp + d.lvl_at, d.lvl_n, j.comp_bytes - d.lvl_at, ns, vals[wave])) {
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            for (uint32_t e = lane; e < ns; e += 64) {
-                const uint32_t v = vals[wave][e];
-                if (v < nl) atomicAdd(&mine[v], 1u);
-            }
+    for (uint32_t k = 0; k < CPW; k++) {
+        kind[k] = 0;
+        ns[k] = 0;
+        if (c0 + k < C) {
+            d[k] = j.chunks[c0 + k];
+            ns[k] = d[k].nseq_last & 0x7fffffffu;
+            if (desc_in_bounds(j, d[k], K) && (d[k].out_base >> j.block_log2) < j.n_blocks)
+                kind[k] = d[k].lvl_n == ns[k] ? 1u : 2u;
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (lane < nl) {
-        uint32_t cnt = 0;
 #pragma unroll
-        for (uint32_t k = 0; k < HCOPIES; k++) cnt += h[k * (ORD_LEVELS + 1) + lane];
-        B.ocnt[(size_t)lane * C + c] = cnt;
+    for (uint32_t k = 0; k < CPW; k++)
+#pragma unroll
+        for (uint32_t r = 0; r < ROUNDS; r++) {
+            const uint32_t e = 4 * lane + 4 * 64 * r;
+            w4[k][r] = kind[k] == 1 && e < ns[k] ? bytes4(j.comp + d[k].lvl_at, e, ns[k]) : 0u;
+        }
+    static_assert(CPW == 2, "the counting loop picks chunk k's values by selects");
+#pragma unroll 1
+    for (uint32_t k = 0; k < CPW; k++) {  // not unrolled: one copy of the counting code
+        const uint32_t c = c0 + k;
+        if (c >= C) break;
+        const uint32_t kk = k ? kind[1] : kind[0], n = k ? ns[1] : ns[0];
+        for (uint32_t i = lane; i < HCOPIES * (ORD_LEVELS + 1); i += 64) h[i] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the wave's LDS accesses stay in program order
+        if (kk == 1) {
+#pragma unroll
+            for (uint32_t r = 0; r < ROUNDS; r++) {
+                const uint32_t e = 4 * lane + 4 * 64 * r;
+                const uint32_t wr = k ? w4[1][r] : w4[0][r];
+#pragma unroll
+                for (uint32_t b = 0; b < 4; b++) {
+                    const uint32_t v = (wr >> (8 * b)) & 0xffu;
+                    if (e + b < n && v < nl) atomicAdd(&mine[v], 1u);
+                }
+            }
+        } else if (kk == 2) {
+            const uint32_t at = k ? d[1].lvl_at : d[0].lvl_at, nb = k ? d[1].lvl_n : d[0].lvl_n;
+            if (wave_varints(j.comp + at, nb, j.comp_bytes - at, n, vals[wave])) {
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                for (uint32_t e = lane; e < n; e += 64) {
+                    const uint32_t v = vals[wave][e];
+                    if (v < nl) atomicAdd(&mine[v], 1u);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane < nl) {
+            uint32_t cnt = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < HCOPIES; q++) cnt += h[q * (ORD_LEVELS + 1) + lane];
+            B.ocnt[(size_t)lane * C + c] = cnt;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -1279,21 +1307,6 @@ __global__ void __launch_bounds__(NT) k_otiles(Batch B)
     if (threadIdx.x == 0) B.otile[blockIdx.x] = (uint32_t)tot;
 }
 
-// One workgroup: the tile sums become the tiles' first slots.
-__global__ void __launch_bounds__(NT) k_otscan(Batch B, uint32_t ntiles)
-{
-    __shared__ uint64_t tmp[NT / 64];
-    uint64_t carry = 0;
-    for (uint32_t s0 = 0; s0 < ntiles; s0 += NT) {
-        const uint32_t i = s0 + threadIdx.x;
-        const uint64_t v = i < ntiles ? B.otile[i] : 0;
-        uint64_t tot;
-        const uint64_t ex = wg_excl_scan64(v, tmp, tot);
-        if (i < ntiles) B.otile[i] = (uint32_t)(carry + ex);
-        carry += tot;
-    }
-}
-
 // Each count becomes its first slot.  The element of each level's first
 // chunk must land on the level's first slot and the last one must end at
 // the last slot, else the stream's chunks and its level table disagree and
@@ -1304,7 +1317,9 @@ __global__ void __launch_bounds__(NT) k_oapply(Batch B)
     const uint32_t C = B.one.n_chunks, nl = B.one.max_level + 1;
     const uint64_t E = (uint64_t)nl * C, t0 = (uint64_t)blockIdx.x * OTILE;
     const uint64_t t1 = min(E, t0 + OTILE);
-    uint64_t carry = B.otile[blockIdx.x];
+    uint64_t before = 0, carry;  // the tiles before this one, summed by the workgroup
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += NT) before += B.otile[i];
+    (void)wg_excl_scan64(before, tmp, carry);
     for (uint64_t s0 = t0; s0 < t1; s0 += NT) {
         const uint64_t i = s0 + threadIdx.x;
         const uint64_t v = i < t1 ? B.ocnt[i] : 0;
@@ -2235,9 +2250,9 @@ void enqueue_single(Batch B, const C *counts, const Tune &tn, hipStream_t st, bo
             PhaseScope ps(PH_PARSE, st, timed);
             if (B.ordered) {  // the chunks' first slots per level, before the parse
                 const uint32_t tiles = (uint32_t)(((uint64_t)(B.max_level + 1) * B.n_chunks + OTILE - 1) / OTILE);
-                hipLaunchKernelGGL(k_count, dim3((B.n_chunks + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, st, B);
+                const uint32_t per_wg = NT / 64 * CPW;  // chunks per k_count workgroup
+                hipLaunchKernelGGL(k_count, dim3((B.n_chunks + per_wg - 1) / per_wg), dim3(NT), 0, st, B);
                 hipLaunchKernelGGL(k_otiles, dim3(tiles), dim3(NT), 0, st, B);
-                hipLaunchKernelGGL(k_otscan, dim3(1), dim3(NT), 0, st, B, tiles);
                 hipLaunchKernelGGL(k_oapply, dim3(tiles), dim3(NT), 0, st, B);
             }
             launch_parse<false>(B, B.n_chunks, st);
