@@ -35,8 +35,8 @@ GIB_KIB = 1 << 20  # counters are reported in KiB
 
 EDGE = 12  # level launches of a deep stream listed one by one at each end
 GRID_BANDS = (1 << 20, 1 << 18, 1 << 16, 1 << 14, 0)  # grid-size bands of the other level launches
-GROUP_OF = {"k_map": "setup", "k_setup": "setup", "k_count": "parse", "k_otiles": "parse", "k_otscan": "parse",
-            "k_oapply": "parse", "k_parse": "parse", "k_level": "levels", "k_tail": "levels"}
+GROUP_OF = {"k_map": "setup", "k_setup": "setup", "k_count": "parse", "k_otiles": "parse", "k_oapply": "parse",
+            "k_parse": "parse", "k_level": "levels", "k_tail": "levels"}
 
 
 def source_sha256() -> str:
