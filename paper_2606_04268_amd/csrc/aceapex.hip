@@ -6,7 +6,7 @@
 //
 //   k_map     (batches) global block and chunk indices -> stream
 //   k_setup   one workgroup per block checks the block table, block header and
-//             chunk index and writes a 48-byte descriptor per chunk (absolute
+//             chunk index and writes a 64-byte descriptor per chunk (absolute
 //             slices of cmd/len/lvl/lit/off and the output span).  The first
 //             workgroups also clear each stream's status and level cursors;
 //             for a single stream, workgroup 0 turns the stream's level table
@@ -21,7 +21,12 @@
 //             The literal runs are placed, as whole aligned words, in an LDS
 //             image of the chunk's output span, which is written with aligned
 //             16-byte stores (Sec. 3.2); every match becomes a 12-byte record
-//             (dst, src, len | stream << 21) in the slots of its level.
+//             (dst, src, len | stream << 21) in the slots of its level (on
+//             deep streams grouped by level in LDS first).
+//   k_count, k_otiles, k_oapply  (large single streams of at most 64 levels,
+//             before k_parse) count each chunk's matches per level and scan
+//             the counts, so that k_parse places every level's records in
+//             output order instead of taking their slots with atomics.
 //   k_seal    (batches) record slots a corrupt stream left unfilled get length 0.
 //   k_level   one launch per level k (Sec. 7.1): the copies of level k read
 //             only bytes written by literals or by lower levels and are
@@ -32,9 +37,10 @@
 //             level after level, separated by workgroup barriers: one CU, so
 //             no cache maintenance between levels.
 //
-// k_parse, k_level and k_tail are compiled twice: for one stream, whose
-// output, size and status are kernel arguments, and for batches, where each
-// chunk and record names its stream.  A plan (aceapex_plan_*) lays a batch out
+// k_parse, k_level and k_tail are compiled for one stream, whose output, size
+// and status are kernel arguments, and for batches, where each chunk and
+// record names its stream (k_parse also in three LDS shapes by the deepest
+// level, and once more for ordered slots).  A plan (aceapex_plan_*) lays a batch out
 // once and replays the same launches, optionally as a captured HIP graph.
 //
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
