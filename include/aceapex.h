@@ -140,7 +140,8 @@ int aceapex_level_table(const void *h_stream_prefix, size_t h_len, uint32_t *cou
 /* Device workspace, in bytes, that aceapex_decode_many needs for these n
  * descriptors (n = 1 for aceapex_decode): per chunk a 64-byte descriptor of
  * its slices of the Sec. 3.2 streams, per level of Sec. 7.1 three slot
- * counters, and 12 bytes per match for the level-grouped match records
+ * counters (n = 1: the fill counter on a 128-byte line of its own), and 12
+ * bytes per match for the level-grouped match records
  * (n = 1 and at most 64 levels: also 4 bytes per (level, chunk) for the
  * ordered record slots described at aceapex_decode); for a stream without
  * levels, the workspace of aceapex_decode_derive; with
